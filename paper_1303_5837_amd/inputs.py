@@ -1,0 +1,54 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module only draws random numbers and lays them out; it holds none of the
+factorization's arithmetic.  Every matrix is column-major (Fortran order), and
+``standard_normal`` fills it in column-major order: element (i, j) is draw
+number ``j*m + i`` of a ``numpy.random.default_rng(seed)`` (PCG64) stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# One seed per workload; sub-streams come from SeedSequence(seed).spawn.
+SEEDS = {
+    "tsqr_4096x32": 1,
+    "caqr_8192sq": 2,
+    "tsqr_1Mx64": 3,
+    "batched_tsqr": 4,
+    "mixed_ls": 5,
+    "served_ls": 6,
+}
+
+
+def gaussian(m: int, n: int, seed: int, dtype=np.float64) -> np.ndarray:
+    """m-by-n iid N(0,1), column-major draw order, Fortran layout."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(m * n).reshape(n, m).T  # (i, j) = draw j*m + i
+    a = np.asfortranarray(a)
+    if dtype != np.float64:
+        a = np.asfortranarray(a.astype(dtype))  # round-to-nearest of the same draws
+    return a
+
+
+def substreams(seed: int, k: int) -> list[np.random.Generator]:
+    return [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(k)]
+
+
+def log_uniform_int(rng: np.random.Generator, lo: int, hi: int, size: int) -> np.ndarray:
+    """Integers round(exp(U[ln lo, ln hi]))."""
+    return np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size))).astype(np.int64)
+
+
+def batched_tsqr_sizes(count: int = 2000, seed: int = SEEDS["batched_tsqr"]):
+    """Sizes of the uneven batch: m log-uniform in [256, 65536], n uniform on {8,16,32,64}."""
+    rng = np.random.default_rng(seed)
+    m = log_uniform_int(rng, 256, 65536, count)
+    n = rng.choice(np.array([8, 16, 32, 64]), size=count)
+    return m, n
+
+
+def geometric_singular_values(n: int, kappa: float) -> np.ndarray:
+    """s_i = kappa^(-(i-1)/(n-1)), i = 1..n, so s_1 = 1 and s_n = 1/kappa."""
+    if n == 1:
+        return np.ones(1)
+    return kappa ** (-np.arange(n) / (n - 1.0))
