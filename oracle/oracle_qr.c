@@ -23,8 +23,9 @@
  * H = I - 2 e_1 e_1^T (an exact sign flip), and when x(2:) == 0 and x(1) >= 0 it
  * is the identity.
  *
- * Norms use power-of-two scaling: x is scaled by 2^-e, e = ilogb(max|x|), which
- * is exact, so neither overflow nor underflow spoils sigma = ||x(2:)||^2.
+ * Norms use power-of-two scaling: x is scaled by 2^-e, e = ilogb(max|x|), with
+ * ldexp on each element, which is exact for every finite input (subnormals
+ * included), so neither overflow nor underflow spoils sigma = ||x(2:)||^2.
  *
  * Storage: R in the upper triangle of A, v_j(j+1:m) below the diagonal,
  * beta_j in beta[j].  Column-major with leading dimension lda.
@@ -80,12 +81,13 @@ static void house(int64_t len, double *x, double *beta, double *mu) {
     *mu = 0.0;
     return;
   }
+  /* scale by 2^-e elementwise: exact for every finite x, subnormals included
+   * (a separate factor 2^-e would overflow for e < -1023) */
   int e = ilogb(amax);
-  double s = ldexp(1.0, -e); /* exact power of two */
-  double x1 = x[0] * s;
+  double x1 = ldexp(x[0], -e);
   double sigma = 0.0; /* ||x(2:)||^2 of the scaled vector */
   for (int64_t i = 1; i < len; ++i) {
-    double t = x[i] * s;
+    double t = ldexp(x[i], -e);
 #if ORACLE_MUTANT == 1
     /* planted mistake: drop the last term of sigma */
     if (i == len - 1) t = 0.0;
@@ -115,7 +117,7 @@ static void house(int64_t len, double *x, double *beta, double *mu) {
   v1 = x1 + m; /* planted mistake: wrong sign in v(1) */
 #endif
   double b = 2.0 * v1 * v1 / (sigma + v1 * v1);
-  for (int64_t i = 1; i < len; ++i) x[i] = (x[i] * s) / v1;
+  for (int64_t i = 1; i < len; ++i) x[i] = ldexp(x[i], -e) / v1;
   *beta = b;
   *mu = ldexp(m, e); /* undo the exact scaling */
 }

@@ -109,9 +109,16 @@ def pin_invariants(lib):
     e1, e2 = oracle.factorization_error(A, Q, f.R), oracle.orthogonality_error(Q)
     if not (e1 <= 1e-14 and e2 <= 1e-13):
         return _res(False, f"||A-QR||={e1:.3e} ||I-QtQ||={e2:.3e}")
-    for k in (-600, -3, 5, 700):
+    for k in (-1000, -600, -3, 5, 700, 1000):
         if not np.array_equal(oracle.qr(np.ldexp(A, k), lib).R, np.ldexp(f.R, k)):
             return _res(False, f"scaling by 2^{k} not exact")
+    # subnormal input: the norm's power-of-two scaling must stay finite
+    As = np.ldexp(A[:50, :6], -1060)
+    Rs = oracle.qr(As, lib).R
+    if not np.all(np.isfinite(Rs)):
+        return _res(False, "subnormal input gives a non-finite R")
+    if oracle.rel_fro(np.ldexp(np.abs(np.diag(Rs)), 1060), np.abs(np.diag(oracle.qr(np.ldexp(As, 1060), lib).R))) > 1e-3:
+        return _res(False, "subnormal input: wrong R diagonal")
     # apply_q(apply_qt(C)) = C
     C = rng.standard_normal((700, 5))
     back = f.apply_q(f.apply_qt(C))
