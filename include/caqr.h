@@ -1,0 +1,193 @@
+/*
+ * caqr.h -- C ABI of the multilevel (tree) Householder QR library for one
+ * AMD MI355X (gfx950).
+ *
+ * What it computes.  The QR factorization A = QR of an m-by-n real matrix,
+ * m >= n, Q orthogonal and R upper triangular, obtained with Householder
+ * reflections; Q is kept implicit in compact Y T Y^T form and the reflectors
+ * are stored in the lower part of A along a reduction tree (paper, Section 3.1
+ * "Multilevel QR factorization", and Algorithm 1, ML-CAQR(A, m, n, r, P)).
+ *
+ *   tsqr_factor : one panel (n <= 64): a binary reduction tree of stacked-R
+ *                 eliminations over row blocks (the panel step of Algorithm 1
+ *                 and items 1(a)-1(b) of its description in Section 3.1).
+ *   caqr_factor : the panel loop of Algorithm 1: factor panel kk with the tree,
+ *                 then update the trailing matrix with the leaf reflectors
+ *                 (the MLUPFACT step) and the tree-node reflectors (the
+ *                 MLUPELIM step).
+ *   apply_q     : multiply by Q or Q^T using the stored tree of reflectors.
+ *   ls_solve    : min ||A x - b||_2 via A = QR (the least-squares use named in
+ *                 Section 3.1).
+ *
+ * Conventions shared by every call.
+ *   - Matrices are column-major (Fortran order) FP64 with a leading
+ *     dimension; all matrix pointers are DEVICE pointers of the handle's GPU.
+ *   - Work is enqueued on the handle's stream and returns without waiting;
+ *     caqr_sync() waits and reports asynchronous device errors.
+ *   - Arguments are validated synchronously; on any error nothing is enqueued
+ *     and no output is touched.
+ *   - R is returned with a non-negative diagonal: the library records
+ *     D = diag(sign(R_jj)) (sign(0) = +1) and folds it into Q, so that
+ *     A = Q_thin R with Q_thin = Q_implicit(:, 0:n) D.  For full-rank A this R
+ *     is unique, whatever the tree shape or leaf height.
+ *   - Factorization never fails numerically: a rank-deficient A gives R_jj = 0
+ *     and no error.  NaN/Inf in A propagate.
+ *   - A handle is not thread-safe; use one handle per host thread.  Separate
+ *     handles on separate streams may run concurrently.
+ *
+ * Storage of the factors.  A is overwritten: R in A(0:n, 0:n) (upper
+ * triangle), leaf reflectors Y below the diagonal of each leaf block, and each
+ * tree node's reflector block V (upper triangular, non-unit diagonal) over the
+ * R slot of the row block it eliminated.  tau, T and D live in the factors
+ * object.  The caller keeps A alive and unmodified while the factors are used.
+ */
+#ifndef CAQR_H
+#define CAQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct caqr_handle_s *caqr_handle_t;   /* device, stream, workspace */
+typedef struct caqr_factors_s *caqr_factors_t; /* tau/T/D buffers, tree metadata; references A */
+
+typedef enum {
+  CAQR_SUCCESS = 0,
+  CAQR_ERR_INVALID_VALUE = 1, /* bad size, leading dimension, pointer or option */
+  CAQR_ERR_ALLOC = 2,         /* device allocation failed or exceeds the workspace limit */
+  CAQR_ERR_DEVICE = 3,        /* no usable GPU, or an asynchronous device error */
+  CAQR_ERR_NOT_SUPPORTED = 4, /* valid request outside what is implemented (e.g. m < n) */
+  CAQR_ERR_SINGULAR = 5,      /* ls_solve: R has an exactly zero diagonal entry */
+  CAQR_ERR_NONFINITE = 6,     /* ls_solve: NaN/Inf in R's diagonal or in the solution */
+  CAQR_ERR_NOT_CONVERGED = 7  /* reserved for iterative refinement */
+} caqr_status_t;
+
+typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
+
+/* Tree options (all fields 0 = library default).
+ *   leaf_rows      rows per leaf block: 64, 128 or 256 (default 256).
+ *   leaves_per_wg  leaves one workgroup factors and combines in its own
+ *                  registers/LDS before the device-wide tree: 1, 2 or 4
+ *                  (default 4 for tsqr_factor, 1 for caqr_factor panels).
+ * The tree is always the binary tree over leaves that pairs leaf i with leaf
+ * i + 2^(k-1) at level k (i a multiple of 2^k), the lower index on top;
+ * leaves_per_wg only decides which levels run inside a workgroup, so R, Y, V
+ * and tau are identical for every leaves_per_wg. */
+typedef struct {
+  int32_t leaf_rows;
+  int32_t leaves_per_wg;
+  int32_t reserved0;
+  int32_t reserved1;
+} caqr_tree_opts_t;
+
+/* Summary of a factors object (host values). */
+typedef struct {
+  int64_t m, n, nb;       /* problem size and panel width */
+  int64_t panels;         /* number of panels (1 for tsqr_factor with n <= 64) */
+  int32_t leaf_rows;      /* leaf height used */
+  int32_t leaves_per_wg;  /* leaves per workgroup used */
+  int64_t leaves_panel0;  /* leaves of the first panel */
+  int32_t depth_panel0;   /* tree levels of the first panel */
+  int32_t t_formed;       /* 1 when the T factors are materialized */
+} caqr_factors_info_t;
+
+/* Least-squares options and report. */
+typedef struct {
+  int32_t reserved; /* 0 */
+} caqr_ls_opts_t;
+
+typedef struct {
+  int32_t status; /* caqr_status_t of the solve (valid after caqr_sync) */
+  int64_t index;  /* first j with R_jj == 0 when status == CAQR_ERR_SINGULAR */
+} caqr_ls_info_t;
+
+/* Argument checks run before the handle is inspected, so every size or
+ * pointer error is reported identically whether or not a GPU is present; a
+ * NULL handle with otherwise valid arguments is CAQR_ERR_INVALID_VALUE. */
+
+/* ---------------------------------------------------------------- handles */
+
+/* Create a handle on GPU `device` (its current stream is the null stream).
+ * Returns CAQR_ERR_DEVICE if the device does not exist or no GPU is present;
+ * *h is then set to NULL.  h must not be NULL. */
+caqr_status_t caqr_create(caqr_handle_t *h, int device);
+
+/* Destroy a handle and free its workspace (waits for its stream first). */
+caqr_status_t caqr_destroy(caqr_handle_t h);
+
+/* Set the stream (a hipStream_t passed as void*; NULL = null stream) on which
+ * every later call of this handle enqueues its work. */
+caqr_status_t caqr_set_stream(caqr_handle_t h, void *stream);
+caqr_status_t caqr_get_stream(caqr_handle_t h, void **stream);
+
+/* Upper bound, in bytes, on the device memory the library may hold for this
+ * handle and for each factors object it creates (0 = unlimited).  A call that
+ * would exceed it returns CAQR_ERR_ALLOC without enqueuing anything. */
+caqr_status_t caqr_set_workspace_limit(caqr_handle_t h, size_t bytes);
+
+/* Wait for all work enqueued by this handle; report asynchronous errors. */
+caqr_status_t caqr_sync(caqr_handle_t h);
+
+/* Static English text for a status code. */
+const char *caqr_status_string(caqr_status_t s);
+
+/* Number of visible GPUs (0 when none); never fails. */
+int caqr_device_count(void);
+
+/* -------------------------------------------------------- factorizations */
+
+/* QR of one tall-skinny panel by the binary reduction tree (n <= 64; larger
+ * n is factored panel by panel as caqr_factor with nb = 64).
+ *   m, n   sizes, m >= n >= 0 (m < n: CAQR_ERR_NOT_SUPPORTED).
+ *   A      device, m-by-n, lda >= max(1, m); overwritten with R and the
+ *          reflectors (see the storage note above).
+ *   opts   NULL for defaults.
+ *   F      receives a new factors object (owned by the caller, release with
+ *          caqr_factors_destroy); it references A.
+ * Only tau is stored; the T factors are formed on first use by apply_q. */
+caqr_status_t tsqr_factor(caqr_handle_t h, int64_t m, int64_t n, double *A, int64_t lda,
+                          const caqr_tree_opts_t *opts, caqr_factors_t *F);
+
+/* QR of a general m-by-n matrix (m >= n) panel by panel, panel width nb
+ * (1 <= nb <= 64; nb > n is clamped to n).  Each panel is factored by the
+ * reduction tree and the trailing matrix is updated with the leaf and node
+ * reflectors before the next panel.  Arguments as tsqr_factor. */
+caqr_status_t caqr_factor(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
+                          const caqr_tree_opts_t *opts, caqr_factors_t *F);
+
+/* C <- op(Q) C where Q is the m-by-m orthogonal factor of F (including the
+ * sign matrix D), C is m-by-k in device memory with ldc >= max(1, m), k >= 0.
+ * op = CAQR_OP_T gives Q^T C (so (Q^T A)(0:n, :) = R), op = CAQR_OP_N gives Q C
+ * (so Q [I_n; 0] = Q_thin).  The handle must be on F's device. */
+caqr_status_t apply_q(caqr_handle_t h, caqr_factors_t F, caqr_op_t op, int64_t k, double *C, int64_t ldc);
+
+/* Release a factors object (does not touch A). */
+caqr_status_t caqr_factors_destroy(caqr_factors_t F);
+
+/* Host summary of F. */
+caqr_status_t caqr_factors_get_info(caqr_factors_t F, caqr_factors_info_t *info);
+
+/* Copy the recorded signs D (n doubles, each +1 or -1) to host memory. */
+caqr_status_t caqr_factors_get_signs(caqr_handle_t h, caqr_factors_t F, double *d_host);
+
+/* ------------------------------------------------------- least squares */
+
+/* Solve min ||A x - b|| for each of the nrhs columns of B (m >= n).
+ * A (m-by-n, lda) is overwritten by its factorization, B (m-by-nrhs, ldb >=
+ * max(1, m)) by Q^T B with the solutions in B(0:n, :).  o may be NULL.
+ * The call waits for its stream and returns the numerical status:
+ * CAQR_ERR_SINGULAR (info->index = first j with R_jj == 0) or
+ * CAQR_ERR_NONFINITE (NaN/Inf in R's diagonal or in the solution); info (host
+ * memory, may be NULL) receives the same status.  Argument errors are
+ * reported before anything is enqueued. */
+caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
+                       int64_t ldb, const caqr_ls_opts_t *o, caqr_ls_info_t *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAQR_H */

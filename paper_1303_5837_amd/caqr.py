@@ -1,0 +1,267 @@
+"""Thin Python binding of the C ABI in ``include/caqr.h`` (``libcaqr.so``).
+
+Argument marshalling only: every step of the factorization runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the current
+stream.  Matrices are column-major: an m-by-n matrix is a CUDA float64 tensor
+of shape (m, n) with strides (1, ldx), ldx >= m (see :func:`fortran`).
+
+There is no CPU fallback: if the library is not built this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcaqr.so")
+
+OP_N, OP_T = 0, 1
+
+_STATUS = {
+    0: "CAQR_SUCCESS",
+    1: "CAQR_ERR_INVALID_VALUE",
+    2: "CAQR_ERR_ALLOC",
+    3: "CAQR_ERR_DEVICE",
+    4: "CAQR_ERR_NOT_SUPPORTED",
+    5: "CAQR_ERR_SINGULAR",
+    6: "CAQR_ERR_NONFINITE",
+    7: "CAQR_ERR_NOT_CONVERGED",
+}
+
+
+class CaqrError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {_STATUS.get(code, code)} ({_lib().caqr_status_string(code).decode()})")
+
+
+class TreeOpts(ctypes.Structure):
+    _fields_ = [("leaf_rows", ctypes.c_int32), ("leaves_per_wg", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+class FactorsInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nb", ctypes.c_int64), ("panels", ctypes.c_int64),
+                ("leaf_rows", ctypes.c_int32), ("leaves_per_wg", ctypes.c_int32),
+                ("leaves_panel0", ctypes.c_int64), ("depth_panel0", ctypes.c_int32), ("t_formed", ctypes.c_int32)]
+
+
+class LsOpts(ctypes.Structure):
+    _fields_ = [("reserved", ctypes.c_int32)]
+
+
+class LsInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("index", ctypes.c_int64)]
+
+
+_lib_obj = None
+_lib_lock = threading.Lock()
+
+EXPORTS = [
+    "caqr_create", "caqr_destroy", "caqr_set_stream", "caqr_get_stream", "caqr_set_workspace_limit", "caqr_sync",
+    "caqr_status_string", "caqr_device_count", "tsqr_factor", "caqr_factor", "apply_q", "caqr_factors_destroy",
+    "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve",
+]
+
+
+def _lib():
+    global _lib_obj
+    with _lib_lock:
+        if _lib_obj is not None:
+            return _lib_obj
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        L.caqr_create.argtypes = [ctypes.POINTER(vp), i32]
+        L.caqr_destroy.argtypes = [vp]
+        L.caqr_set_stream.argtypes = [vp, vp]
+        L.caqr_get_stream.argtypes = [vp, ctypes.POINTER(vp)]
+        L.caqr_set_workspace_limit.argtypes = [vp, ctypes.c_size_t]
+        L.caqr_sync.argtypes = [vp]
+        L.caqr_status_string.argtypes = [i32]
+        L.caqr_status_string.restype = ctypes.c_char_p
+        L.caqr_device_count.argtypes = []
+        L.tsqr_factor.argtypes = [vp, i64, i64, vp, i64, ctypes.POINTER(TreeOpts), ctypes.POINTER(vp)]
+        L.caqr_factor.argtypes = [vp, i64, i64, i64, vp, i64, ctypes.POINTER(TreeOpts), ctypes.POINTER(vp)]
+        L.apply_q.argtypes = [vp, vp, i32, i64, vp, i64]
+        L.caqr_factors_destroy.argtypes = [vp]
+        L.caqr_factors_get_info.argtypes = [vp, ctypes.POINTER(FactorsInfo)]
+        L.caqr_factors_get_signs.argtypes = [vp, vp, dp]
+        L.ls_solve.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(LsOpts), ctypes.POINTER(LsInfo)]
+        for name in EXPORTS:
+            if name not in ("caqr_status_string",):
+                getattr(L, name).restype = ctypes.c_int
+        _lib_obj = L
+        return L
+
+
+def library() -> ctypes.CDLL:
+    """The loaded ``libcaqr.so`` (raises if it is not built)."""
+    return _lib()
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise CaqrError(code, where)
+
+
+def device_count() -> int:
+    return int(_lib().caqr_device_count())
+
+
+class Handle:
+    """A library handle on one GPU; calls enqueue on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        self.device = device
+        _check(_lib().caqr_create(ctypes.byref(self._h), device), "caqr_create")
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def use_current_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(_lib().caqr_set_stream(self._h, ctypes.c_void_p(s)), "caqr_set_stream")
+
+    def set_workspace_limit(self, nbytes: int):
+        _check(_lib().caqr_set_workspace_limit(self._h, nbytes), "caqr_set_workspace_limit")
+
+    def sync(self):
+        _check(_lib().caqr_sync(self._h), "caqr_sync")
+
+    def close(self):
+        if self._h:
+            _lib().caqr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles: dict = {}
+
+
+def handle(device: int = 0) -> Handle:
+    """A cached handle per (thread, device)."""
+    key = (threading.get_ident(), device)
+    h = _handles.get(key)
+    if h is None:
+        h = _handles[key] = Handle(device)
+    h.use_current_stream()
+    return h
+
+
+def fortran(x, device="cuda") -> torch.Tensor:
+    """Copy a 2-D array into a column-major float64 CUDA tensor."""
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if t.ndim == 1:
+        t = t[:, None]
+    out = torch.empty((t.shape[1], t.shape[0]), dtype=torch.float64, device=device).t()
+    out.copy_(t)
+    return out
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dtype != torch.float64 or not t.is_cuda or t.ndim != 2:
+        raise ValueError("expected a 2-D float64 CUDA tensor")
+    m, n = t.shape
+    if t.stride(0) != 1 and not (n <= 1 and t.is_contiguous()):
+        raise ValueError("matrix must be column-major (stride (1, ld))")
+    return max(1, t.stride(1) if n > 1 else m)
+
+
+def _opts(leaf_rows=0, leaves_per_wg=0):
+    if not leaf_rows and not leaves_per_wg:
+        return None
+    return ctypes.byref(TreeOpts(leaf_rows, leaves_per_wg, 0, 0))
+
+
+class Factors:
+    """Owner of a ``caqr_factors_t``; keeps the factored tensor alive."""
+
+    def __init__(self, h: Handle, ptr: ctypes.c_void_p, A: torch.Tensor):
+        self.h, self._f, self.A = h, ptr, A
+
+    def info(self) -> FactorsInfo:
+        inf = FactorsInfo()
+        _check(_lib().caqr_factors_get_info(self._f, ctypes.byref(inf)), "caqr_factors_get_info")
+        return inf
+
+    def signs(self):
+        import numpy as np
+
+        d = np.zeros(self.A.shape[1])
+        _check(_lib().caqr_factors_get_signs(self.h.ptr, self._f, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "caqr_factors_get_signs")
+        return d
+
+    @property
+    def R(self) -> torch.Tensor:
+        n = self.A.shape[1]
+        return torch.triu(self.A[:n, :n])
+
+    def apply_q(self, C: torch.Tensor, op: int = OP_T) -> torch.Tensor:
+        """In place: C <- Q^T C (op=OP_T) or Q C (op=OP_N)."""
+        self.h.use_current_stream()
+        if C.shape[0] != self.A.shape[0]:
+            raise ValueError("C must have m rows")
+        _check(_lib().apply_q(self.h.ptr, self._f, op, C.shape[1], ctypes.c_void_p(C.data_ptr()), _ld(C)), "apply_q")
+        return C
+
+    def q_thin(self) -> torch.Tensor:
+        m, n = self.A.shape
+        Q = torch.zeros((n, m), dtype=torch.float64, device=self.A.device).t()
+        Q[:n, :n] = torch.eye(n, dtype=torch.float64, device=self.A.device)
+        return self.apply_q(Q, OP_N)
+
+    def close(self):
+        if self._f:
+            _lib().caqr_factors_destroy(self._f)
+            self._f = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tsqr(A: torch.Tensor, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0) -> Factors:
+    """In place TSQR of a column-major CUDA tensor; returns the factors (R = F.R)."""
+    h = handle(device)
+    m, n = A.shape
+    f = ctypes.c_void_p()
+    _check(_lib().tsqr_factor(h.ptr, m, n, ctypes.c_void_p(A.data_ptr()), _ld(A), _opts(leaf_rows, leaves_per_wg),
+                              ctypes.byref(f)), "tsqr_factor")
+    return Factors(h, f, A)
+
+
+def caqr(A: torch.Tensor, nb: int = 64, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0) -> Factors:
+    """In place CAQR (panel width nb) of a column-major CUDA tensor."""
+    h = handle(device)
+    m, n = A.shape
+    f = ctypes.c_void_p()
+    _check(_lib().caqr_factor(h.ptr, m, n, nb, ctypes.c_void_p(A.data_ptr()), _ld(A), _opts(leaf_rows, leaves_per_wg),
+                              ctypes.byref(f)), "caqr_factor")
+    return Factors(h, f, A)
+
+
+def ls_solve(A: torch.Tensor, B: torch.Tensor, device: int = 0):
+    """Least squares in place: returns (X = B[:n], info); raises CaqrError on a numerical failure."""
+    h = handle(device)
+    m, n = A.shape
+    info = LsInfo()
+    code = _lib().ls_solve(h.ptr, m, n, B.shape[1], ctypes.c_void_p(A.data_ptr()), _ld(A),
+                           ctypes.c_void_p(B.data_ptr()), _ld(B), None, ctypes.byref(info))
+    if code not in (0, 5, 6):
+        _check(code, "ls_solve")
+    return B[:n], info

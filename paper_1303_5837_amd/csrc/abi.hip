@@ -1,0 +1,507 @@
+// C ABI and host runtime: handles, factors objects, argument validation, the
+// panel loop of ML-CAQR (paper, Algorithm 1: factor panel kk, then update the
+// trailing matrix with the leaf and tree-node reflectors) and the
+// least-squares driver.  Every numerical step runs in the HIP kernels of this
+// library; this file only validates, allocates, plans and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/caqr.h"
+#include "kernels.hpp"
+
+using namespace caqr;
+
+namespace {
+
+constexpr int kNbMax = 64;
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+__global__ void fill_u32_kernel(unsigned *p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+struct PanelRec {
+  int64_t row0 = 0, col0 = 0;  // origin of the panel in A (row0 == col0)
+  int64_t m = 0;               // panel rows
+  int b = 0;                   // panel width
+  int L = 0;                   // leaves
+  double *tau_leaf = nullptr, *tau_node = nullptr, *d = nullptr;
+  double *T_leaf = nullptr, *T_node = nullptr;
+};
+
+int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+struct caqr_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t ws_limit = 0;             // 0 = unlimited
+  unsigned *tickets = nullptr;     // panel tickets [cap/2], update tickets [cap/2]
+  size_t tickets_cap = 0;          // total counters
+  int64_t *status_dev = nullptr;   // 2 words for ls_solve
+};
+
+struct caqr_factors_s {
+  int device = 0;
+  int64_t m = 0, n = 0, nb = 0, lda = 0;
+  double *A = nullptr;
+  int leaf_rows = 256, lpw = 1;
+  std::vector<PanelRec> panels;
+  double *small = nullptr;  // tau and d of all panels
+  double *tbuf = nullptr;   // T of all panels (eager for caqr_factor, lazy for tsqr_factor)
+  size_t tbuf_bytes = 0;
+  bool t_formed = false;
+  size_t limit = 0;
+};
+
+namespace {
+
+caqr_status_t to_status(hipError_t e) { return e == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE; }
+
+// Ensure `need` zeroed ticket counters in each half of the handle's buffer.
+caqr_status_t ensure_tickets(caqr_handle_t h, size_t need) {
+  if (need * 2 <= h->tickets_cap) return CAQR_SUCCESS;
+  size_t cap = std::max<size_t>(need * 2, 1 << 16);
+  if (h->ws_limit && cap * sizeof(unsigned) > h->ws_limit) return CAQR_ERR_ALLOC;
+  if (h->tickets) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+    (void)hipFree(h->tickets);
+    h->tickets = nullptr;
+    h->tickets_cap = 0;
+  }
+  unsigned *p = nullptr;
+  if (hipMalloc(&p, cap * sizeof(unsigned)) != hipSuccess) return CAQR_ERR_ALLOC;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, h->stream, p, cap);
+  if (hipGetLastError() != hipSuccess) {
+    (void)hipFree(p);
+    return CAQR_ERR_DEVICE;
+  }
+  h->tickets = p;
+  h->tickets_cap = cap;
+  return CAQR_SUCCESS;
+}
+
+unsigned *panel_tickets(caqr_handle_t h) { return h->tickets; }
+unsigned *update_tickets(caqr_handle_t h) { return h->tickets + h->tickets_cap / 2; }
+
+int resolve_leaf_rows(const caqr_tree_opts_t *o) {
+  return (o && o->leaf_rows) ? o->leaf_rows : 256;
+}
+
+bool valid_leaf_rows(int h) { return h == 64 || h == 128 || h == 256; }
+
+// Plan the panels of an m-by-n factorization with panel width nb and build
+// the factors object (buffers for tau, d and optionally T).
+caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda, int leaf_rows,
+                           int lpw, bool eager_t, caqr_factors_t *out) {
+  caqr_factors_s *F = new (std::nothrow) caqr_factors_s;
+  if (!F) return CAQR_ERR_ALLOC;
+  F->device = h->device;
+  F->m = m;
+  F->n = n;
+  F->nb = nb;
+  F->lda = lda;
+  F->A = A;
+  F->leaf_rows = leaf_rows;
+  F->lpw = lpw;
+  F->limit = h->ws_limit;
+  size_t small_doubles = 0, t_doubles = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += nb) {
+    PanelRec p;
+    p.row0 = c0;
+    p.col0 = c0;
+    p.m = m - c0;
+    p.b = (int)std::min<int64_t>(nb, n - c0);
+    p.L = ceil_div(p.m, leaf_rows);
+    F->panels.push_back(p);
+    small_doubles += (size_t)p.L * 2 * kNbMax + kNbMax;
+    t_doubles += (size_t)p.L * 2 * kNbMax * kNbMax;
+  }
+  const size_t small_bytes = small_doubles * sizeof(double);
+  const size_t t_bytes = t_doubles * sizeof(double);
+  const size_t need = small_bytes + (eager_t ? t_bytes : 0);
+  if (h->ws_limit && need > h->ws_limit) {
+    delete F;
+    return CAQR_ERR_ALLOC;
+  }
+  if (small_bytes && hipMalloc(&F->small, small_bytes) != hipSuccess) {
+    delete F;
+    return CAQR_ERR_ALLOC;
+  }
+  double *q = F->small;
+  for (auto &p : F->panels) {
+    p.tau_leaf = q;
+    q += (size_t)p.L * kNbMax;
+    p.tau_node = q;
+    q += (size_t)p.L * kNbMax;
+    p.d = q;
+    q += kNbMax;
+  }
+  F->tbuf_bytes = t_bytes;
+  if (eager_t && t_bytes) {
+    if (hipMalloc(&F->tbuf, t_bytes) != hipSuccess) {
+      (void)hipFree(F->small);
+      delete F;
+      return CAQR_ERR_ALLOC;
+    }
+    double *t = F->tbuf;
+    for (auto &p : F->panels) {
+      p.T_leaf = t;
+      t += (size_t)p.L * kNbMax * kNbMax;
+      p.T_node = t;
+      t += (size_t)p.L * kNbMax * kNbMax;
+    }
+    F->t_formed = true;
+  }
+  *out = F;
+  return CAQR_SUCCESS;
+}
+
+PanelParams panel_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p) {
+  PanelParams pp;
+  pp.A = F->A + p.row0 + p.col0 * F->lda;
+  pp.lda = F->lda;
+  pp.m = p.m;
+  pp.b = p.b;
+  pp.L = p.L;
+  pp.lpw = F->lpw;
+  pp.tau_leaf = p.tau_leaf;
+  pp.tau_node = p.tau_node;
+  pp.T_leaf = p.T_leaf;
+  pp.T_node = p.T_node;
+  pp.d = p.d;
+  pp.tickets = panel_tickets(h);
+  return pp;
+}
+
+UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p, double *C, int64_t ldc, int64_t k) {
+  UpdateParams u;
+  u.Y = F->A + p.row0 + p.col0 * F->lda;
+  u.ldy = F->lda;
+  u.C = C + p.row0;
+  u.ldc = ldc;
+  u.m = p.m;
+  u.k = k;
+  u.b = p.b;
+  u.L = p.L;
+  u.h = F->leaf_rows;
+  u.T_leaf = p.T_leaf;
+  u.T_node = p.T_node;
+  u.d = p.d;
+  u.tickets = update_tickets(h);
+  u.tiles = ceil_div(k, 64);
+  u.level = 0;
+  return u;
+}
+
+// Factor every panel in order, updating the trailing matrix after each one.
+caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) {
+  size_t need = 0;
+  for (auto &p : F->panels) {
+    need = std::max<size_t>(need, (size_t)p.L);
+    const int64_t k = F->n - p.col0 - p.b;
+    if (k > 0) need = std::max<size_t>(need, (size_t)p.L * ceil_div(k, 64));
+  }
+  caqr_status_t st = ensure_tickets(h, need);
+  if (st) return st;
+  for (auto &p : F->panels) {
+    PanelParams pp = panel_params(h, F, p);
+    hipError_t e = launch_tsqr_panel(pp, F->leaf_rows, form_t, h->stream);
+    if (e != hipSuccess) return CAQR_ERR_DEVICE;
+    const int64_t k = F->n - p.col0 - p.b;
+    if (k > 0) {
+      UpdateParams u = update_params(h, F, p, F->A + (p.col0 + p.b) * F->lda, F->lda, k);
+      e = launch_apply_qt(u, h->stream);
+      if (e != hipSuccess) return CAQR_ERR_DEVICE;
+    }
+  }
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t ensure_t(caqr_handle_t h, caqr_factors_t F) {
+  if (F->t_formed || F->panels.empty()) return CAQR_SUCCESS;
+  if (F->limit && F->tbuf_bytes > F->limit) return CAQR_ERR_ALLOC;
+  if (hipMalloc(&F->tbuf, F->tbuf_bytes) != hipSuccess) return CAQR_ERR_ALLOC;
+  double *t = F->tbuf;
+  for (auto &p : F->panels) {
+    p.T_leaf = t;
+    t += (size_t)p.L * kNbMax * kNbMax;
+    p.T_node = t;
+    t += (size_t)p.L * kNbMax * kNbMax;
+    FormTParams f;
+    f.Y = F->A + p.row0 + p.col0 * F->lda;
+    f.ldy = F->lda;
+    f.m = p.m;
+    f.b = p.b;
+    f.L = p.L;
+    f.h = F->leaf_rows;
+    f.tau_leaf = p.tau_leaf;
+    f.tau_node = p.tau_node;
+    f.T_leaf = p.T_leaf;
+    f.T_node = p.T_node;
+    if (launch_form_t(f, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+  }
+  F->t_formed = true;
+  return CAQR_SUCCESS;
+}
+
+// Size and pointer checks come first, then the handle, so that every argument
+// error is reported the same way with or without a device.
+caqr_status_t check_opts(const caqr_tree_opts_t *o);
+
+caqr_status_t check_common(caqr_handle_t h, int64_t m, int64_t n, const double *A, int64_t lda, caqr_factors_t *F,
+                           const caqr_tree_opts_t *opts) {
+  if (!F) return CAQR_ERR_INVALID_VALUE;
+  if (check_opts(opts)) return CAQR_ERR_INVALID_VALUE;
+  if (m < 0 || n < 0 || lda < std::max<int64_t>(1, m)) return CAQR_ERR_INVALID_VALUE;
+  if (n > 0 && !A) return CAQR_ERR_INVALID_VALUE;
+  if (m < n) return CAQR_ERR_NOT_SUPPORTED;
+  if (n > INT32_MAX || m / std::max<int64_t>(n, 1) > ((int64_t)1 << 40)) return CAQR_ERR_NOT_SUPPORTED;
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t check_opts(const caqr_tree_opts_t *o) {
+  if (!o) return CAQR_SUCCESS;
+  if (o->leaf_rows && !valid_leaf_rows(o->leaf_rows)) return CAQR_ERR_INVALID_VALUE;
+  if (o->leaves_per_wg && o->leaves_per_wg != 1 && o->leaves_per_wg != 2 && o->leaves_per_wg != 4)
+    return CAQR_ERR_INVALID_VALUE;
+  if (o->reserved0 || o->reserved1) return CAQR_ERR_INVALID_VALUE;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
+                          const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr) {
+  const int hr = resolve_leaf_rows(opts);
+  const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : (tsqr ? 4 : 1);
+  DeviceGuard g(h->device);
+  caqr_factors_t f = nullptr;
+  caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, &f);
+  if (st) return st;
+  if (n > 0) {
+    st = run_factorization(h, f, !tsqr);
+    if (st) {
+      caqr_factors_destroy(f);
+      return st;
+    }
+  }
+  *F = f;
+  return CAQR_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *caqr_status_string(caqr_status_t s) {
+  switch (s) {
+    case CAQR_SUCCESS: return "success";
+    case CAQR_ERR_INVALID_VALUE: return "invalid value";
+    case CAQR_ERR_ALLOC: return "allocation failed or workspace limit exceeded";
+    case CAQR_ERR_DEVICE: return "device error or no usable GPU";
+    case CAQR_ERR_NOT_SUPPORTED: return "not supported";
+    case CAQR_ERR_SINGULAR: return "R is exactly singular";
+    case CAQR_ERR_NONFINITE: return "non-finite value in R or in the solution";
+    case CAQR_ERR_NOT_CONVERGED: return "iterative refinement did not converge";
+  }
+  return "unknown status";
+}
+
+int caqr_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+caqr_status_t caqr_create(caqr_handle_t *h, int device) {
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  *h = nullptr;
+  const int n = caqr_device_count();
+  if (device < 0 || device >= n) return CAQR_ERR_DEVICE;
+  caqr_handle_s *p = new (std::nothrow) caqr_handle_s;
+  if (!p) return CAQR_ERR_ALLOC;
+  p->device = device;
+  DeviceGuard g(device);
+  if (hipMalloc(&p->status_dev, 2 * sizeof(int64_t)) != hipSuccess) {
+    delete p;
+    return CAQR_ERR_ALLOC;
+  }
+  *h = p;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_destroy(caqr_handle_t h) {
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  DeviceGuard g(h->device);
+  caqr_status_t st = to_status(hipStreamSynchronize(h->stream));
+  if (h->tickets) (void)hipFree(h->tickets);
+  if (h->status_dev) (void)hipFree(h->status_dev);
+  delete h;
+  return st;
+}
+
+caqr_status_t caqr_set_stream(caqr_handle_t h, void *stream) {
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  h->stream = (hipStream_t)stream;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_get_stream(caqr_handle_t h, void **stream) {
+  if (!h || !stream) return CAQR_ERR_INVALID_VALUE;
+  *stream = (void *)h->stream;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_set_workspace_limit(caqr_handle_t h, size_t bytes) {
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  h->ws_limit = bytes;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_sync(caqr_handle_t h) {
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  DeviceGuard g(h->device);
+  return to_status(hipStreamSynchronize(h->stream));
+}
+
+caqr_status_t tsqr_factor(caqr_handle_t h, int64_t m, int64_t n, double *A, int64_t lda, const caqr_tree_opts_t *opts,
+                          caqr_factors_t *F) {
+  caqr_status_t st = check_common(h, m, n, A, lda, F, opts);
+  if (st) return st;
+  if (n > kNbMax) return factor_impl(h, m, n, kNbMax, A, lda, opts, F, false);
+  return factor_impl(h, m, n, std::max<int64_t>(n, 1), A, lda, opts, F, true);
+}
+
+caqr_status_t caqr_factor(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
+                          const caqr_tree_opts_t *opts, caqr_factors_t *F) {
+  if (nb < 1 || nb > kNbMax) return CAQR_ERR_INVALID_VALUE;
+  caqr_status_t st = check_common(h, m, n, A, lda, F, opts);
+  if (st) return st;
+  nb = std::min<int64_t>(nb, std::max<int64_t>(n, 1));
+  return factor_impl(h, m, n, nb, A, lda, opts, F, false);
+}
+
+caqr_status_t apply_q(caqr_handle_t h, caqr_factors_t F, caqr_op_t op, int64_t k, double *C, int64_t ldc) {
+  if (op != CAQR_OP_N && op != CAQR_OP_T) return CAQR_ERR_INVALID_VALUE;
+  if (!h || !F) return CAQR_ERR_INVALID_VALUE;
+  if (k < 0 || ldc < std::max<int64_t>(1, F->m) || (k > 0 && !C)) return CAQR_ERR_INVALID_VALUE;
+  if (h->device != F->device) return CAQR_ERR_INVALID_VALUE;
+  if (k == 0 || F->n == 0) return CAQR_SUCCESS;
+  DeviceGuard g(h->device);
+  caqr_status_t st = ensure_t(h, F);
+  if (st) return st;
+  size_t need = 0;
+  for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L * ceil_div(k, 64));
+  if ((st = ensure_tickets(h, need))) return st;
+  if (op == CAQR_OP_T) {
+    for (auto &p : F->panels) {
+      UpdateParams u = update_params(h, F, p, C, ldc, k);
+      if (launch_apply_qt(u, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+    }
+  } else {
+    for (auto it = F->panels.rbegin(); it != F->panels.rend(); ++it) {
+      UpdateParams u = update_params(h, F, *it, C, ldc, k);
+      if (launch_apply_qn(u, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+    }
+  }
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_factors_destroy(caqr_factors_t F) {
+  if (!F) return CAQR_ERR_INVALID_VALUE;
+  DeviceGuard g(F->device);
+  // the buffers may still be read by enqueued kernels: wait for the device first
+  (void)hipDeviceSynchronize();
+  if (F->small) (void)hipFree(F->small);
+  if (F->tbuf) (void)hipFree(F->tbuf);
+  delete F;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_factors_get_info(caqr_factors_t F, caqr_factors_info_t *info) {
+  if (!F || !info) return CAQR_ERR_INVALID_VALUE;
+  std::memset(info, 0, sizeof(*info));
+  info->m = F->m;
+  info->n = F->n;
+  info->nb = F->nb;
+  info->panels = (int64_t)F->panels.size();
+  info->leaf_rows = F->leaf_rows;
+  info->leaves_per_wg = F->lpw;
+  if (!F->panels.empty()) {
+    info->leaves_panel0 = F->panels[0].L;
+    int depth = 0;
+    while ((1 << depth) < F->panels[0].L) ++depth;
+    info->depth_panel0 = depth;
+  }
+  info->t_formed = F->t_formed ? 1 : 0;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_factors_get_signs(caqr_handle_t h, caqr_factors_t F, double *d_host) {
+  if (!h || !F || (!d_host && F->n > 0)) return CAQR_ERR_INVALID_VALUE;
+  DeviceGuard g(h->device);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+  for (auto &p : F->panels)
+    if (hipMemcpy(d_host + p.col0, p.d, (size_t)p.b * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return CAQR_ERR_DEVICE;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
+                       int64_t ldb, const caqr_ls_opts_t *o, caqr_ls_info_t *info) {
+  if (m < 0 || n < 0 || nrhs < 0 || lda < std::max<int64_t>(1, m) || ldb < std::max<int64_t>(1, m))
+    return CAQR_ERR_INVALID_VALUE;
+  if ((n > 0 && !A) || (nrhs > 0 && !B)) return CAQR_ERR_INVALID_VALUE;
+  if (o && o->reserved) return CAQR_ERR_INVALID_VALUE;
+  if (m < n) return CAQR_ERR_NOT_SUPPORTED;
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  if (info) {
+    info->status = CAQR_SUCCESS;
+    info->index = 0;
+  }
+  if (n == 0 || nrhs == 0) return CAQR_SUCCESS;
+  DeviceGuard g(h->device);
+  caqr_factors_t F = nullptr;
+  caqr_status_t st = (n <= kNbMax) ? tsqr_factor(h, m, n, A, lda, nullptr, &F)
+                                   : caqr_factor(h, m, n, kNbMax, A, lda, nullptr, &F);
+  if (st) return st;
+  st = apply_q(h, F, CAQR_OP_T, nrhs, B, ldb);
+  if (!st && launch_trsm_upper(A, lda, n, B, ldb, nrhs, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
+  if (!st && launch_check_solution(A, lda, n, B, ldb, nrhs, h->status_dev, h->stream) != hipSuccess)
+    st = CAQR_ERR_DEVICE;
+  int64_t stat[2] = {0, 0};
+  if (!st && hipMemcpyAsync(stat, h->status_dev, sizeof(stat), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+    st = CAQR_ERR_DEVICE;
+  if (!st && hipStreamSynchronize(h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
+  caqr_factors_destroy(F);
+  if (st) return st;
+  caqr_status_t num = CAQR_SUCCESS;
+  if (stat[0] > 0)
+    num = CAQR_ERR_SINGULAR;
+  else if (stat[1])
+    num = CAQR_ERR_NONFINITE;
+  if (info) {
+    info->status = num;
+    info->index = stat[0] > 0 ? stat[0] - 1 : 0;
+  }
+  return num;
+}
+
+}  // extern "C"

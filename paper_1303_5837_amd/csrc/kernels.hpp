@@ -1,0 +1,75 @@
+// Kernel parameter blocks and launchers (host and device side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace caqr {
+
+// One panel of the factorization: rows [0, m) x columns [0, b) at A (lda).
+struct PanelParams {
+  double *A;
+  int64_t lda;
+  int64_t m;
+  int b;          // panel width, 1..64
+  int L;          // number of leaves (row blocks of leaf_rows rows)
+  int lpw;        // leaves per workgroup (1, 2, 4)
+  double *tau_leaf;   // [L][64]
+  double *tau_node;   // [L][64], node id = eliminated leaf (1..L-1)
+  double *T_leaf;     // [L][64*64] column-major, or null
+  double *T_node;     // [L][64*64], or null
+  double *d;          // [64] signs of the root R
+  unsigned *tickets;  // [L], zero on entry and on exit
+};
+
+// Application of one panel's Q (or Q^T) to C (m rows x k columns at C, ldc).
+// Leaves, nodes and their reflectors as produced by the panel kernel.
+struct UpdateParams {
+  const double *Y;    // panel origin (reflectors live here), ldy
+  int64_t ldy;
+  double *C;          // rows aligned with the panel's rows
+  int64_t ldc;
+  int64_t m;          // panel rows
+  int64_t k;          // columns of C
+  int b;              // panel width
+  int L;              // leaves
+  int h;              // leaf rows
+  const double *T_leaf;
+  const double *T_node;
+  const double *d;    // signs
+  unsigned *tickets;  // [L * tiles] for the fused tree climb, zero on entry/exit
+  int tiles;          // column tiles of 64
+  int level;          // node kernels: tree level processed (half = 1 << (level-1))
+};
+
+hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, bool form_t, hipStream_t s);
+
+// C <- Q^T C for one panel: leaf updates, then the tree bottom-up (fused with
+// tickets), then rows 0..b-1 scaled by D.
+hipError_t launch_apply_qt(const UpdateParams &u, hipStream_t s);
+
+// C <- Q C for one panel: rows 0..b-1 scaled by D, the tree top-down (one
+// launch per level), then the leaves.
+hipError_t launch_apply_qn(const UpdateParams &u, hipStream_t s);
+
+// T factors of every leaf and node of a panel factored without them.
+struct FormTParams {
+  const double *Y;  // panel origin
+  int64_t ldy;
+  int64_t m;
+  int b, L, h;
+  const double *tau_leaf, *tau_node;
+  double *T_leaf, *T_node;
+};
+hipError_t launch_form_t(const FormTParams &f, hipStream_t s);
+
+// Least squares helpers.
+// Back substitution R X = B (R n-by-n upper, B n-by-nrhs), in place.
+hipError_t launch_trsm_upper(const double *R, int64_t ldr, int64_t n, double *B, int64_t ldb, int64_t nrhs,
+                             hipStream_t s);
+// status[0] <- 0, or 1 + (first j with R_jj == 0); status[1] <- 1 if some R_jj or
+// some entry of X(0:n, :) is not finite.
+hipError_t launch_check_solution(const double *R, int64_t ldr, int64_t n, const double *X, int64_t ldx,
+                                 int64_t nrhs, int64_t *status, hipStream_t s);
+
+}  // namespace caqr

@@ -1,0 +1,90 @@
+"""The C ABI on a host without a GPU: the library loads, exports every symbol
+include/caqr.h declares, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1303_5837_amd import caqr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "caqr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:caqr_status_t|const char \*|int)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["tsqr_factor", "caqr_factor", "apply_q", "ls_solve", "caqr_create", "caqr_destroy",
+                     "caqr_sync", "caqr_factors_destroy"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = caqr.library()
+    names = declared_functions()
+    assert names
+    out = subprocess.run(["nm", "-D", "--defined-only", caqr.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    for n in names:
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+    assert set(caqr.EXPORTS) <= set(names)
+
+
+def _no_gpu():
+    return caqr.device_count() == 0
+
+
+def test_create_without_device():
+    if not _no_gpu():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p(1)
+    assert caqr.library().caqr_create(ctypes.byref(h), 0) == 3  # CAQR_ERR_DEVICE
+    assert not h.value
+
+
+def test_status_strings():
+    lib = caqr.library()
+    for code in range(8):
+        assert lib.caqr_status_string(code)
+    assert b"unknown" in lib.caqr_status_string(99)
+
+
+def _tsqr(m, n, A, lda, opts=None, F=True, h=None):
+    f = ctypes.c_void_p()
+    return caqr.library().tsqr_factor(h, m, n, A, lda, opts, ctypes.byref(f) if F else None)
+
+
+def test_argument_validation_without_device():
+    lib = caqr.library()
+    A = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+    assert _tsqr(10, 20, A, 10) == 4  # m < n: NOT_SUPPORTED
+    assert _tsqr(-1, 2, A, 10) == 1
+    assert _tsqr(10, 2, A, 9) == 1  # lda < m
+    assert _tsqr(10, 2, None, 10) == 1  # A NULL with n > 0
+    assert _tsqr(10, 2, A, 10, F=False) == 1
+    assert _tsqr(10, 2, A, 10) == 1  # valid sizes, NULL handle
+    bad = caqr.TreeOpts(100, 0, 0, 0)
+    assert _tsqr(10, 2, A, 10, ctypes.byref(bad)) == 1
+    bad = caqr.TreeOpts(256, 3, 0, 0)
+    assert _tsqr(10, 2, A, 10, ctypes.byref(bad)) == 1
+    f = ctypes.c_void_p()
+    assert lib.caqr_factor(None, 100, 100, 0, A, 100, None, ctypes.byref(f)) == 1  # nb = 0
+    assert lib.caqr_factor(None, 100, 100, 65, A, 100, None, ctypes.byref(f)) == 1  # nb > 64
+    assert lib.caqr_factor(None, 10, 100, 64, A, 10, None, ctypes.byref(f)) == 4
+    assert lib.apply_q(None, None, 2, 1, A, 10) == 1  # bad op
+    assert lib.apply_q(None, None, 1, 1, A, 10) == 1  # NULL handle / factors
+    assert lib.ls_solve(None, 5, 6, 1, A, 5, A, 5, None, None) == 4
+    assert lib.ls_solve(None, 6, 5, -1, A, 6, A, 6, None, None) == 1
+    assert lib.ls_solve(None, 6, 5, 1, A, 6, A, 5, None, None) == 1  # ldb < m
+    assert lib.ls_solve(None, 6, 5, 1, A, 6, A, 6, None, None) == 1  # NULL handle
+    assert lib.caqr_sync(None) == 1
+    assert lib.caqr_destroy(None) == 1
+    assert lib.caqr_factors_destroy(None) == 1
