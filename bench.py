@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the multilevel QR path on one MI355X.
+
+Headline: CAQR FP64 GFLOP/s on an 8192 x 8192 N(0,1) matrix (seed 2), panel
+width 64, leaf rows 256, binary tree per panel (workgroup leaf, workgroup,
+device), flops counted as LAPACK's 4 n^3 / 3.  One step = one factorization
+(every panel: leaf QR, reduction tree, trailing update).  A is restored from a
+pristine device copy before each step, outside the event-timed factorization.
+
+Also reported: the live roofline of the dominant kernel (the trailing update on
+FP64 MFMA, from HIP events the library records around each launch on its
+stream), the oracle's CPU rate on a bounded sample, and TSQR on 1,048,576 x 64
+and 4096 x 32 as secondary lines.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and MFMA)
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+
+def update_flops(rows: int, cols: int, b: int, leaves: int) -> float:
+    """Algorithmic flops of one Q^T update launch of a panel (rows x b reflectors,
+    `leaves` leaves) on `cols` columns: per leaf W = Y^T C and C -= Y W (4 rows b
+    per column) plus T^T W (b^2 per column); per tree node V^T C2, T^T W and V W
+    on b x b triangles (3 b^2 per column)."""
+    return cols * (4.0 * rows * b + leaves * b * b + 3.0 * (leaves - 1) * b * b)
+
+
+def panel_bytes(rows: int, b: int) -> float:
+    """Algorithmic HBM bytes of one panel factorization: read A, write Y/R."""
+    return 16.0 * rows * b
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design of the sharded variant is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1303_5837_amd import caqr, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n
+    nb = 64
+    A0 = caqr.fortran(inputs.gaussian(n, n, inputs.SEEDS["caqr_8192sq"]), device=dev)
+    A = torch.empty_like(A0.t()).t()
+    h = caqr.handle(0)
+
+    def one_step():
+        A.copy_(A0)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        F = caqr.caqr(A, nb=nb)
+        ev1.record()
+        return F, ev0, ev1
+
+    for _ in range(args.warmup):
+        F, _, _ = one_step()
+        F.close()
+    torch.cuda.synchronize()
+
+    h.set_trace(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    events = []
+    for _ in range(args.steps):
+        F, e0, e1 = one_step()
+        events.append((e0, e1))
+        F.close()  # waits for the device before freeing the factors' buffers
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    trace = h.take_trace()
+    h.set_trace(False)
+    step_ms = [a.elapsed_time(b) for a, b in events]
+    ms = float(np.mean(step_ms))
+    lapack_flops = 4.0 * n ** 3 / 3.0
+    gflops = lapack_flops / (ms * 1e-3) / 1e9
+
+    upd = [e for e in trace if e["kind"] == "update_t"]
+    pan = [e for e in trace if e["kind"] == "panel"]
+    upd_ms = sum(e["ms"] for e in upd)
+    upd_flops = sum(update_flops(e["rows"], e["cols"], e["width"], e["leaves"]) for e in upd)
+    achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    pan_ms = sum(e["ms"] for e in pan)
+
+    out = {
+        "metric": "CAQR FP64 GFLOP/s (% peak); batched LS solves/s + p99 latency vs plain",
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"caqr_fp64_{n}x{n}_nb{nb}", "m": n, "n": n, "nb": nb, "leaf_rows": 256,
+                   "tree": "binary per panel: workgroup leaf, workgroup, device", "seed": inputs.SEEDS["caqr_8192sq"],
+                   "flop_count": "LAPACK 4n^3/3"},
+        "pct_fp64_peak": round(100.0 * gflops / (PEAK_FP64_TFLOPS * 1e3), 2),
+        "step_ms": [round(x, 4) for x in step_ms],
+        "wall_ms_timed_region": round(wall_ms, 2),
+        "roofline": {
+            "kernel": "leaf_update_kernel (trailing update, Q^T, fused tree levels)",
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+            "traffic": None,
+            "launches_per_step": len(upd) // max(1, args.steps),
+            "avg_launch_ms": round(upd_ms / max(1, len(upd)), 5),
+            "update_share_of_step": round(upd_ms / max(1e-9, sum(step_ms)), 4),
+            "panel_share_of_step": round(pan_ms / max(1e-9, sum(step_ms)), 4),
+        },
+    }
+    del F
+    A0 = A = None
+    torch.cuda.empty_cache()
+
+    if not args.no_secondary:
+        sec = {}
+        for (m2, n2, key) in [(1 << 20, 64, "tsqr_1Mx64"), (4096, 32, "tsqr_4096x32")]:
+            B0 = caqr.fortran(inputs.gaussian(m2, n2, inputs.SEEDS[key]), device=dev)
+            B = torch.empty_like(B0.t()).t()
+            times = []
+            reps = 20 if m2 > 4096 else 50
+            for it in range(5 + reps):
+                B.copy_(B0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                G = caqr.tsqr(B)
+                e1.record()
+                torch.cuda.synchronize()
+                if it >= 5:
+                    times.append(e0.elapsed_time(e1))
+                G.close()
+            t = float(np.median(times))
+            gbs = panel_bytes(m2, n2) / (t * 1e-3) / 1e9
+            sec[key] = {"median_us": round(t * 1e3, 2), "p10_us": round(float(np.percentile(times, 10)) * 1e3, 2),
+                        "p90_us": round(float(np.percentile(times, 90)) * 1e3, 2),
+                        "gflops": round((2.0 * m2 * n2 * n2 - 2.0 * n2 ** 3 / 3) / (t * 1e-3) / 1e9, 1),
+                        "algorithmic_GBps": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / PEAK_HBM_GBS, 2)}
+            del B0, B
+        out["secondary"] = sec
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ns = 4096
+        S = inputs.gaussian(ns, ns, inputs.SEEDS["caqr_8192sq"])
+        t0 = time.perf_counter()
+        oracle.qr_r(S)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(4.0 * ns ** 3 / 3.0 / dt / 1e9, 3),
+            "unit": "GFLOP/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle Householder QR of a {ns}x{ns} N(0,1) matrix (seed 2), one run of {dt:.1f} s, "
+                      f"LAPACK flop count 4n^3/3, OpenMP over trailing columns",
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -186,6 +186,36 @@ caqr_status_t caqr_factors_get_signs(caqr_handle_t h, caqr_factors_t F, double *
 caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
                        int64_t ldb, const caqr_ls_opts_t *o, caqr_ls_info_t *info);
 
+/* ------------------------------------------------------------- tracing */
+
+/* Per-launch device timing (HIP events recorded on the handle's stream around
+ * each kernel the library launches), for measurement tools.  Off by default. */
+typedef enum {
+  CAQR_TRACE_PANEL = 0,     /* panel factorization (leaf QR + reduction tree) */
+  CAQR_TRACE_UPDATE_T = 1,  /* Q^T applied to a block of columns (trailing update) */
+  CAQR_TRACE_UPDATE_N = 2,  /* Q applied to a block of columns */
+  CAQR_TRACE_FORM_T = 3,    /* T factors formed after a factorization without them */
+  CAQR_TRACE_OTHER = 4      /* least-squares helpers */
+} caqr_trace_kind_t;
+
+typedef struct {
+  int32_t kind;    /* caqr_trace_kind_t */
+  int32_t panel;   /* panel index within its factorization */
+  int64_t rows;    /* rows of the panel */
+  int64_t cols;    /* panel width (PANEL, FORM_T) or columns updated (UPDATE_*) */
+  int32_t width;   /* panel width b */
+  int32_t leaves;  /* leaves of the panel's tree */
+  double ms;       /* device time of the launch, milliseconds */
+} caqr_trace_entry_t;
+
+/* Enable (1) or disable (0) tracing; either call clears recorded entries. */
+caqr_status_t caqr_set_trace(caqr_handle_t h, int enable);
+
+/* Wait for the handle's stream and copy up to max entries (in launch order) to
+ * host memory; *count receives the number recorded (may exceed max).  Entries
+ * are cleared afterwards. */
+caqr_status_t caqr_trace_read(caqr_handle_t h, caqr_trace_entry_t *out, int64_t max, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,15 @@ class FactorsInfo(ctypes.Structure):
                 ("leaves_panel0", ctypes.c_int64), ("depth_panel0", ctypes.c_int32), ("t_formed", ctypes.c_int32)]
 
 
+class TraceEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("panel", ctypes.c_int32), ("rows", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("width", ctypes.c_int32), ("leaves", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
+TRACE_KINDS = {0: "panel", 1: "update_t", 2: "update_n", 3: "form_t", 4: "other"}
+
+
 class LsOpts(ctypes.Structure):
     _fields_ = [("reserved", ctypes.c_int32)]
 
@@ -63,7 +72,7 @@ _lib_lock = threading.Lock()
 EXPORTS = [
     "caqr_create", "caqr_destroy", "caqr_set_stream", "caqr_get_stream", "caqr_set_workspace_limit", "caqr_sync",
     "caqr_status_string", "caqr_device_count", "tsqr_factor", "caqr_factor", "apply_q", "caqr_factors_destroy",
-    "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve",
+    "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_trace_read",
 ]
 
 
@@ -92,6 +101,8 @@ def _lib():
         L.caqr_factors_get_info.argtypes = [vp, ctypes.POINTER(FactorsInfo)]
         L.caqr_factors_get_signs.argtypes = [vp, vp, dp]
         L.ls_solve.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(LsOpts), ctypes.POINTER(LsInfo)]
+        L.caqr_set_trace.argtypes = [vp, i32]
+        L.caqr_trace_read.argtypes = [vp, ctypes.POINTER(TraceEntry), i64, ctypes.POINTER(i64)]
         for name in EXPORTS:
             if name not in ("caqr_status_string",):
                 getattr(L, name).restype = ctypes.c_int
@@ -134,6 +145,20 @@ class Handle:
 
     def sync(self):
         _check(_lib().caqr_sync(self._h), "caqr_sync")
+
+    def set_trace(self, enable: bool):
+        _check(_lib().caqr_set_trace(self._h, 1 if enable else 0), "caqr_set_trace")
+
+    def take_trace(self, max_entries: int = 1 << 16):
+        """Recorded launches (launch order) with their device time in ms; clears the record."""
+        buf = (TraceEntry * max_entries)()
+        count = ctypes.c_int64()
+        _check(_lib().caqr_trace_read(self._h, buf, max_entries, ctypes.byref(count)), "caqr_trace_read")
+        out = []
+        for e in buf[: min(count.value, max_entries)]:
+            out.append({"kind": TRACE_KINDS.get(e.kind, e.kind), "panel": e.panel, "rows": e.rows, "cols": e.cols,
+                        "width": e.width, "leaves": e.leaves, "ms": e.ms})
+        return out
 
     def close(self):
         if self._h:

@@ -49,13 +49,21 @@ int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
+struct TraceRec {
+  caqr_trace_entry_t e;
+  hipEvent_t start, stop;
+};
+
 struct caqr_handle_s {
   int device = 0;
   hipStream_t stream = nullptr;
   size_t ws_limit = 0;             // 0 = unlimited
-  unsigned *tickets = nullptr;     // panel tickets [cap/2], update tickets [cap/2]
-  size_t tickets_cap = 0;          // total counters
+  unsigned *tickets = nullptr;     // tickets of the panel kernel's device-level tree
+  size_t tickets_cap = 0;          // counters
   int64_t *status_dev = nullptr;   // 2 words for ls_solve
+  bool trace = false;
+  std::vector<TraceRec> trace_recs;   // recorded launches
+  std::vector<hipEvent_t> event_pool; // free events
 };
 
 struct caqr_factors_s {
@@ -75,10 +83,59 @@ namespace {
 
 caqr_status_t to_status(hipError_t e) { return e == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE; }
 
-// Ensure `need` zeroed ticket counters in each half of the handle's buffer.
+hipEvent_t pool_event(caqr_handle_t h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when tracing is on.
+struct TraceScope {
+  caqr_handle_t h;
+  TraceRec rec{};
+  bool on;
+  TraceScope(caqr_handle_t hh, int kind, int panel, int64_t rows, int64_t cols, int width, int leaves)
+      : h(hh), on(hh->trace) {
+    if (!on) return;
+    rec.e.kind = kind;
+    rec.e.panel = panel;
+    rec.e.rows = rows;
+    rec.e.cols = cols;
+    rec.e.width = width;
+    rec.e.leaves = leaves;
+    rec.e.ms = 0.0;
+    rec.start = pool_event(h);
+    rec.stop = pool_event(h);
+    if (!rec.start || !rec.stop) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(rec.start, h->stream);
+  }
+  ~TraceScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.stop, h->stream);
+    h->trace_recs.push_back(rec);
+  }
+};
+
+void trace_clear(caqr_handle_t h) {
+  for (auto &r : h->trace_recs) {
+    h->event_pool.push_back(r.start);
+    h->event_pool.push_back(r.stop);
+  }
+  h->trace_recs.clear();
+}
+
+// Ensure `need` zeroed ticket counters in the handle's buffer.
 caqr_status_t ensure_tickets(caqr_handle_t h, size_t need) {
-  if (need * 2 <= h->tickets_cap) return CAQR_SUCCESS;
-  size_t cap = std::max<size_t>(need * 2, 1 << 16);
+  if (need <= h->tickets_cap) return CAQR_SUCCESS;
+  size_t cap = std::max<size_t>(need, 1 << 14);
   if (h->ws_limit && cap * sizeof(unsigned) > h->ws_limit) return CAQR_ERR_ALLOC;
   if (h->tickets) {
     if (hipStreamSynchronize(h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
@@ -99,7 +156,6 @@ caqr_status_t ensure_tickets(caqr_handle_t h, size_t need) {
 }
 
 unsigned *panel_tickets(caqr_handle_t h) { return h->tickets; }
-unsigned *update_tickets(caqr_handle_t h) { return h->tickets + h->tickets_cap / 2; }
 
 int resolve_leaf_rows(const caqr_tree_opts_t *o) {
   return (o && o->leaf_rows) ? o->leaf_rows : 256;
@@ -205,8 +261,12 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
   u.T_leaf = p.T_leaf;
   u.T_node = p.T_node;
   u.d = p.d;
-  u.tickets = update_tickets(h);
-  u.tiles = ceil_div(k, 64);
+  u.tiles = ceil_div(k, kUpdTile);
+  // leaves per workgroup: the smallest power of two that keeps the grid
+  // within about four workgroups per CU slot pair (256 CUs x 2 slots x 2)
+  int g = 1;
+  while (g < p.L && (int64_t)ceil_div(p.L, g) * u.tiles > 1024) g <<= 1;
+  u.group = g;
   u.level = 0;
   return u;
 }
@@ -214,23 +274,28 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
 // Factor every panel in order, updating the trailing matrix after each one.
 caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) {
   size_t need = 0;
-  for (auto &p : F->panels) {
-    need = std::max<size_t>(need, (size_t)p.L);
-    const int64_t k = F->n - p.col0 - p.b;
-    if (k > 0) need = std::max<size_t>(need, (size_t)p.L * ceil_div(k, 64));
-  }
+  for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L);
   caqr_status_t st = ensure_tickets(h, need);
   if (st) return st;
+  int idx = 0;
   for (auto &p : F->panels) {
     PanelParams pp = panel_params(h, F, p);
-    hipError_t e = launch_tsqr_panel(pp, F->leaf_rows, form_t, h->stream);
+    hipError_t e;
+    {
+      TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L);
+      e = launch_tsqr_panel(pp, F->leaf_rows, form_t, h->stream);
+    }
     if (e != hipSuccess) return CAQR_ERR_DEVICE;
     const int64_t k = F->n - p.col0 - p.b;
     if (k > 0) {
       UpdateParams u = update_params(h, F, p, F->A + (p.col0 + p.b) * F->lda, F->lda, k);
-      e = launch_apply_qt(u, h->stream);
+      {
+        TraceScope ts(h, CAQR_TRACE_UPDATE_T, idx, p.m, k, p.b, p.L);
+        e = launch_apply_qt(u, h->stream);
+      }
       if (e != hipSuccess) return CAQR_ERR_DEVICE;
     }
+    ++idx;
   }
   return CAQR_SUCCESS;
 }
@@ -256,6 +321,7 @@ caqr_status_t ensure_t(caqr_handle_t h, caqr_factors_t F) {
     f.tau_node = p.tau_node;
     f.T_leaf = p.T_leaf;
     f.T_node = p.T_node;
+    TraceScope ts(h, CAQR_TRACE_FORM_T, (int)(&p - &F->panels[0]), p.m, p.b, p.b, p.L);
     if (launch_form_t(f, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
   }
   F->t_formed = true;
@@ -353,8 +419,35 @@ caqr_status_t caqr_destroy(caqr_handle_t h) {
   caqr_status_t st = to_status(hipStreamSynchronize(h->stream));
   if (h->tickets) (void)hipFree(h->tickets);
   if (h->status_dev) (void)hipFree(h->status_dev);
+  trace_clear(h);
+  for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
   delete h;
   return st;
+}
+
+caqr_status_t caqr_set_trace(caqr_handle_t h, int enable) {
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  DeviceGuard g(h->device);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+  trace_clear(h);
+  h->trace = enable != 0;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_trace_read(caqr_handle_t h, caqr_trace_entry_t *out, int64_t max, int64_t *count) {
+  if (!h || !count || max < 0 || (max > 0 && !out)) return CAQR_ERR_INVALID_VALUE;
+  DeviceGuard g(h->device);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+  *count = (int64_t)h->trace_recs.size();
+  for (int64_t i = 0; i < (int64_t)h->trace_recs.size() && i < max; ++i) {
+    TraceRec &r = h->trace_recs[i];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) ms = -1.f;
+    out[i] = r.e;
+    out[i].ms = ms;
+  }
+  trace_clear(h);
+  return CAQR_SUCCESS;
 }
 
 caqr_status_t caqr_set_stream(caqr_handle_t h, void *stream) {
@@ -407,17 +500,16 @@ caqr_status_t apply_q(caqr_handle_t h, caqr_factors_t F, caqr_op_t op, int64_t k
   DeviceGuard g(h->device);
   caqr_status_t st = ensure_t(h, F);
   if (st) return st;
-  size_t need = 0;
-  for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L * ceil_div(k, 64));
-  if ((st = ensure_tickets(h, need))) return st;
   if (op == CAQR_OP_T) {
     for (auto &p : F->panels) {
       UpdateParams u = update_params(h, F, p, C, ldc, k);
+      TraceScope ts(h, CAQR_TRACE_UPDATE_T, (int)(&p - &F->panels[0]), p.m, k, p.b, p.L);
       if (launch_apply_qt(u, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
     }
   } else {
     for (auto it = F->panels.rbegin(); it != F->panels.rend(); ++it) {
       UpdateParams u = update_params(h, F, *it, C, ldc, k);
+      TraceScope ts(h, CAQR_TRACE_UPDATE_N, (int)(&*it - &F->panels[0]), it->m, k, it->b, it->L);
       if (launch_apply_qn(u, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
     }
   }

@@ -6,6 +6,9 @@
 
 namespace caqr {
 
+// Columns of C per workgroup of the update kernels (tickets are per tile).
+constexpr int kUpdTile = 32;
+
 // One panel of the factorization: rows [0, m) x columns [0, b) at A (lda).
 struct PanelParams {
   double *A;
@@ -37,15 +40,17 @@ struct UpdateParams {
   const double *T_leaf;
   const double *T_node;
   const double *d;    // signs
-  unsigned *tickets;  // [L * tiles] for the fused tree climb, zero on entry/exit
-  int tiles;          // column tiles of 64
+  int tiles;          // column tiles of kUpdTile
+  int group;          // leaves per workgroup of the Q^T kernel (power of two)
   int level;          // node kernels: tree level processed (half = 1 << (level-1))
 };
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, bool form_t, hipStream_t s);
 
-// C <- Q^T C for one panel: leaf updates, then the tree bottom-up (fused with
-// tickets), then rows 0..b-1 scaled by D.
+// C <- Q^T C for one panel: leaf updates and the tree bottom-up, then rows
+// 0..b-1 scaled by D.  One workgroup per (group of u.group leaves, tile) runs
+// the leaves and the tree levels inside its group; a second launch runs the
+// levels above the groups.
 hipError_t launch_apply_qt(const UpdateParams &u, hipStream_t s);
 
 // C <- Q C for one panel: rows 0..b-1 scaled by D, the tree top-down (one

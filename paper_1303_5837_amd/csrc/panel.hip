@@ -81,13 +81,16 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
         }
         sig = row16_sum(sig);
         const double alpha = readlane_f64(a[Q][Q], (cj & 3) * 16 + cj);
-        double s2 = fma(alpha, alpha, sig);
-        double mu, sigz;
+        const double s2 = fma(alpha, alpha, sig);
+        // The reflector is formed from x scaled by 2^sh: sh = 0 normally; when
+        // alpha^2 + sigma is zero, subnormal, overflowing or NaN, sh = -ilogb(max|x|)
+        // (ldexp per element is exact), so that mu, tau and 1 / (alpha - beta)
+        // are computed on normal numbers.
+        int sh = 0;
+        double alpha_s = alpha, sig_s = sig, mu_s;
         if (s2 >= DBL_MIN && s2 <= DBL_MAX) {
-          mu = sqrt(s2);
-          sigz = sig;
+          mu_s = sqrt(s2);
         } else {
-          // zero, subnormal, overflowing or NaN: redo with exact 2^-e scaling
           double mx = 0.0;
 #pragma unroll
           for (int i = 0; i < NACT; ++i) {
@@ -97,37 +100,35 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
             mx = inx ? fmax(mx, fabs(a[i][Q])) : mx;
           }
           mx = row16_max(mx);
-          if (mx == 0.0 || !(mx <= DBL_MAX)) {
-            mu = (mx == 0.0) ? 0.0 : sqrt(s2);
-            sigz = (mx == 0.0) ? 0.0 : sig;
+          if (mx == 0.0 || !(mx <= DBL_MAX)) {  // zero column, or Inf/NaN (propagated)
+            mu_s = (mx == 0.0) ? 0.0 : sqrt(s2);
+            sig_s = (mx == 0.0) ? 0.0 : sig;
           } else {
-            // ldexp per element: exact for every finite value, subnormals
-            // included (a factor 2^-ex would overflow for ex < -1023)
-            const int ex = ilogb(mx);
+            sh = -ilogb(mx);
             double ss = 0.0;
 #pragma unroll
             for (int i = 0; i < NACT; ++i) {
               const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
               if (!act) continue;
               const bool below = (i > Q) || (r > cj);
-              const double e = ldexp(a[i][Q], -ex);
+              const double e = ldexp(a[i][Q], sh);
               ss = below ? fma(e, e, ss) : ss;
             }
-            ss = row16_sum(ss);
-            const double as = ldexp(alpha, -ex);
-            mu = ldexp(sqrt(fma(as, as, ss)), ex);
-            sigz = ss;
+            sig_s = row16_sum(ss);
+            alpha_s = ldexp(alpha, sh);
+            mu_s = sqrt(fma(alpha_s, alpha_s, sig_s));
           }
         }
         double beta, tau, scal;
-        if (sigz == 0.0) {
+        if (sig_s == 0.0) {
           beta = alpha;
           tau = 0.0;
           scal = 0.0;
         } else {
-          beta = -copysign(mu, alpha);
-          tau = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
+          const double beta_s = -copysign(mu_s, alpha_s);
+          tau = (beta_s - alpha_s) / beta_s;
+          scal = 1.0 / (alpha_s - beta_s);
+          beta = ldexp(beta_s, -sh);
         }
 #pragma unroll
         for (int i = 0; i < NACT; ++i) {
@@ -135,7 +136,7 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
           if (!act) continue;
           double vv;
           if (i > Q || r > cj) {
-            vv = a[i][Q] * scal;
+            vv = ldexp(a[i][Q], sh) * scal;
             a[i][Q] = vv;
           } else if (r == cj && i == Q) {
             vv = 1.0;
