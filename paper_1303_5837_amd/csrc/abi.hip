@@ -64,6 +64,8 @@ struct caqr_handle_s {
   bool trace = false;
   std::vector<TraceRec> trace_recs;   // recorded launches
   std::vector<hipEvent_t> event_pool; // free events
+  hipStream_t side = nullptr;         // look-ahead stream (default priority, created on first use)
+  hipEvent_t sync_ev[2] = {nullptr, nullptr};  // ordering events between the two streams
 };
 
 struct caqr_factors_s {
@@ -94,13 +96,16 @@ hipEvent_t pool_event(caqr_handle_t h) {
   return e;
 }
 
-// Brackets one launch with events when tracing is on.
+// Brackets one launch with events (on the stream it is launched on) when
+// tracing is on.
 struct TraceScope {
   caqr_handle_t h;
+  hipStream_t stream;
   TraceRec rec{};
   bool on;
-  TraceScope(caqr_handle_t hh, int kind, int panel, int64_t rows, int64_t cols, int width, int leaves)
-      : h(hh), on(hh->trace) {
+  TraceScope(caqr_handle_t hh, int kind, int panel, int64_t rows, int64_t cols, int width, int leaves,
+             hipStream_t st = nullptr)
+      : h(hh), stream(st ? st : hh->stream), on(hh->trace) {
     if (!on) return;
     rec.e.kind = kind;
     rec.e.panel = panel;
@@ -115,11 +120,11 @@ struct TraceScope {
       on = false;
       return;
     }
-    (void)hipEventRecord(rec.start, h->stream);
+    (void)hipEventRecord(rec.start, stream);
   }
   ~TraceScope() {
     if (!on) return;
-    (void)hipEventRecord(rec.stop, h->stream);
+    (void)hipEventRecord(rec.stop, stream);
     h->trace_recs.push_back(rec);
   }
 };
@@ -271,31 +276,65 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
   return u;
 }
 
-// Factor every panel in order, updating the trailing matrix after each one.
+// Side stream and ordering events for the look-ahead (created once per handle).
+caqr_status_t ensure_side(caqr_handle_t h) {
+  if (h->side) return CAQR_SUCCESS;
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+    h->side = nullptr;
+    return CAQR_ERR_DEVICE;
+  }
+  for (auto &e : h->sync_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return CAQR_ERR_DEVICE;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form_t, hipStream_t st) {
+  const PanelRec &p = F->panels[idx];
+  PanelParams pp = panel_params(h, F, p);
+  TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
+  return launch_tsqr_panel(pp, F->leaf_rows, form_t, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
+}
+
+// Q_idx^T applied to the columns [c0, c0 + k) of A (rows of the panel).
+caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_t c0, int64_t k) {
+  const PanelRec &p = F->panels[idx];
+  UpdateParams u = update_params(h, F, p, F->A + c0 * F->lda, F->lda, k);
+  TraceScope ts(h, CAQR_TRACE_UPDATE_T, idx, p.m, k, p.b, p.L);
+  return launch_apply_qt(u, h->stream) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
+}
+
+// Factor every panel in order, updating the trailing matrix after each one
+// (the panel loop of Algorithm 1).  With more than one panel the loop looks
+// ahead: the next panel's columns are updated first, the next panel is
+// factored on a second stream while the rest of the trailing matrix is
+// updated, and the following update waits for it.  Every launch is ordered
+// by stream order or by an event, and all work ends on the handle's stream.
 caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) {
   size_t need = 0;
   for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L);
   caqr_status_t st = ensure_tickets(h, need);
   if (st) return st;
-  int idx = 0;
-  for (auto &p : F->panels) {
-    PanelParams pp = panel_params(h, F, p);
-    hipError_t e;
-    {
-      TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L);
-      e = launch_tsqr_panel(pp, F->leaf_rows, form_t, h->stream);
+  const int P = (int)F->panels.size();
+  const bool ahead = P > 1;
+  if (ahead && (st = ensure_side(h))) return st;
+  if ((st = launch_panel(h, F, 0, form_t, h->stream))) return st;
+  for (int idx = 0; idx < P; ++idx) {
+    const PanelRec &p = F->panels[idx];
+    const int64_t c0 = p.col0 + p.b;
+    const int64_t k = F->n - c0;
+    if (k <= 0) break;
+    if (!ahead || idx + 1 >= P) {
+      if ((st = launch_trailing(h, F, idx, c0, k))) return st;
+      continue;
     }
-    if (e != hipSuccess) return CAQR_ERR_DEVICE;
-    const int64_t k = F->n - p.col0 - p.b;
-    if (k > 0) {
-      UpdateParams u = update_params(h, F, p, F->A + (p.col0 + p.b) * F->lda, F->lda, k);
-      {
-        TraceScope ts(h, CAQR_TRACE_UPDATE_T, idx, p.m, k, p.b, p.L);
-        e = launch_apply_qt(u, h->stream);
-      }
-      if (e != hipSuccess) return CAQR_ERR_DEVICE;
-    }
-    ++idx;
+    const int64_t kn = F->panels[idx + 1].b;  // columns of the next panel
+    if ((st = launch_trailing(h, F, idx, c0, kn))) return st;
+    if (hipEventRecord(h->sync_ev[0], h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+    if (hipStreamWaitEvent(h->side, h->sync_ev[0], 0) != hipSuccess) return CAQR_ERR_DEVICE;
+    if ((st = launch_panel(h, F, idx + 1, form_t, h->side))) return st;
+    if (hipEventRecord(h->sync_ev[1], h->side) != hipSuccess) return CAQR_ERR_DEVICE;
+    if (k > kn && (st = launch_trailing(h, F, idx, c0 + kn, k - kn))) return st;
+    if (hipStreamWaitEvent(h->stream, h->sync_ev[1], 0) != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return CAQR_SUCCESS;
 }
@@ -417,6 +456,12 @@ caqr_status_t caqr_destroy(caqr_handle_t h) {
   if (!h) return CAQR_ERR_INVALID_VALUE;
   DeviceGuard g(h->device);
   caqr_status_t st = to_status(hipStreamSynchronize(h->stream));
+  if (h->side) {
+    if (hipStreamSynchronize(h->side) != hipSuccess) st = CAQR_ERR_DEVICE;
+    (void)hipStreamDestroy(h->side);
+  }
+  for (auto &e : h->sync_ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->tickets) (void)hipFree(h->tickets);
   if (h->status_dev) (void)hipFree(h->status_dev);
   trace_clear(h);

@@ -152,32 +152,46 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
         }
       }
       __syncthreads();
-      // ---- every thread: w = v^T A(:, col) for its column slots, then the rank-1 update
+      // ---- every thread: w = v^T A(:, col) for its column slots, then the rank-1 update.
+      // v is read from LDS where it is used (not held across the reductions).
+      // Slots whose columns are all finished (q < Q) are skipped unless their
+      // dot products are needed for T (G = Y^T Y).
       const double tau = sm.tau[par];
-      double vv[NACT];
+      const double *vrow = sm.v[par] + r;
+      double p[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) p[q] = 0.0;
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
         const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
-        vv[i] = act ? sm.v[par][16 * i + r] : 0.0;
+        if (!act) continue;
+        const double vi = vrow[16 * i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (!FORM_T && q < Q) continue;
+          p[q] = fma(vi, a[i][q], p[q]);
+        }
       }
+      double coef[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        double p = 0.0;
-#pragma unroll
-        for (int i = 0; i < NACT; ++i) {
-          const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
-          if (act) p = fma(vv[i], a[i][q], p);
-        }
-        const double w = row16_sum(p);
+        if (!FORM_T && q < Q) continue;
+        const double w = row16_sum(p[q]);
         const int col = c + 16 * q;
         if (FORM_T) {
           if (r == 0 && col < j) sm.G[col * kLdG + j] = w;
         }
-        const double coef = (col > j && col < b) ? tau * w : 0.0;
+        coef[q] = (col > j && col < b) ? tau * w : 0.0;
+      }
 #pragma unroll
-        for (int i = 0; i < NACT; ++i) {
-          const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
-          if (act) a[i][q] = fma(-coef, vv[i], a[i][q]);
+      for (int i = 0; i < NACT; ++i) {
+        const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
+        if (!act) continue;
+        const double vi = vrow[16 * i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (q < Q) continue;  // finished columns are never updated
+          a[i][q] = fma(-coef[q], vi, a[i][q]);
         }
       }
     }
@@ -351,25 +365,45 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) 
     const int leaf = leaf0 + li;
     const int64_t row0 = (int64_t)leaf * H;
     // ---- level 1: factor the leaf block in registers
-#pragma unroll
-    for (int i = 0; i < NCH; ++i)
+    // uniform fast path: the whole leaf in range and the panel 16*NQ wide
+    const bool full = row0 + H <= p.m && p.b == 16 * NQ;
+    if (full) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int64_t grow = row0 + 16 * i + r;
-        const int col = c + 16 * q;
-        a[i][q] = (i < RPT && grow < p.m && col < p.b) ? *pan(p, grow, col) : 0.0;
+        const double *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) a[i][q] = (i < RPT) ? colp[16 * i] : 0.0;
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NCH; ++i)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int64_t grow = row0 + 16 * i + r;
+          const int col = c + 16 * q;
+          a[i][q] = (i < RPT && grow < p.m && col < p.b) ? *pan(p, grow, col) : 0.0;
+        }
+    }
     clear_g(sm);
     __syncthreads();
     householder_steps<NCH, NQ, RPT, false, FORM_T>(a, p.b, sm);
-#pragma unroll
-    for (int i = 0; i < RPT; ++i)
+    if (full) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int64_t grow = row0 + 16 * i + r;
-        const int col = c + 16 * q;
-        if (grow < p.m && col < p.b) *pan(p, grow, col) = a[i][q];
+        double *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) colp[16 * i] = a[i][q];
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int64_t grow = row0 + 16 * i + r;
+          const int col = c + 16 * q;
+          if (grow < p.m && col < p.b) *pan(p, grow, col) = a[i][q];
+        }
+    }
     __syncthreads();
     if (threadIdx.x < kMaxB)
       p.tau_leaf[(int64_t)leaf * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : 0.0;

@@ -416,7 +416,7 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
 // become complete inside the group (binary pairs i, i + 2^(k-1), the lower
 // index on top).  A single group covers the whole tree and also applies D.
 // No workgroup depends on another, so no device-scope synchronization is
-// needed; the levels above the groups run in tree_top_kernel afterwards.
+// needed; the levels above the groups run afterwards, one launch per level.
 template <int NQ, int RT>
 __global__ void __launch_bounds__(kThreads, 2) qt_group_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
@@ -433,17 +433,6 @@ __global__ void __launch_bounds__(kThreads, 2) qt_group_kernel(UpdateParams u) {
     for (int node = first + half; node < last; node += 2 * half)
       node_update<NQ, true>(u, node - half, node, tile, sm, vec_ok);
   if (ngroups == 1) scale_top_rows(u, tile);
-}
-
-// Levels of the tree above the groups (pairs of group roots), then D.
-template <int NQ>
-__global__ void __launch_bounds__(kThreads, 2) qt_top_kernel(UpdateParams u) {
-  __shared__ UpdSmem sm;
-  const int tile = blockIdx.x;
-  const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
-  for (int half = u.group; half < u.L; half <<= 1)
-    for (int node = half; node < u.L; node += 2 * half) node_update<NQ, true>(u, node - half, node, tile, sm, vec_ok);
-  scale_top_rows(u, tile);
 }
 
 // Q applied (not transposed): leaves only, no tree (the tree runs first, top-down).
@@ -475,7 +464,19 @@ template <int NQ, int RT>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   const int ngroups = (u.L + u.group - 1) / u.group;
   hipLaunchKernelGGL((qt_group_kernel<NQ, RT>), dim3(ngroups * u.tiles), dim3(kThreads), 0, s, u);
-  if (ngroups > 1) hipLaunchKernelGGL((qt_top_kernel<NQ>), dim3(u.tiles), dim3(kThreads), 0, s, u);
+  if (ngroups > 1) {
+    // levels above the groups, one launch per level (nodes of a level in parallel), then D
+    int lev = 1;
+    while ((1 << (lev - 1)) < u.group) ++lev;
+    for (; (1 << (lev - 1)) < u.L; ++lev) {
+      UpdateParams v = u;
+      v.level = lev;
+      const int half = 1 << (lev - 1);
+      const int per = (u.L + half - 1) / (2 * half) + 1;
+      hipLaunchKernelGGL((node_level_kernel<NQ, true>), dim3(per * u.tiles), dim3(kThreads), 0, s, v);
+    }
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kThreads), 0, s, u);
+  }
   return hipGetLastError();
 }
 
