@@ -245,8 +245,6 @@ PanelParams panel_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p) {
   pp.lpw = F->lpw;
   pp.tau_leaf = p.tau_leaf;
   pp.tau_node = p.tau_node;
-  pp.T_leaf = p.T_leaf;
-  pp.T_node = p.T_node;
   pp.d = p.d;
   pp.tickets = panel_tickets(h);
   return pp;
@@ -288,11 +286,34 @@ caqr_status_t ensure_side(caqr_handle_t h) {
   return CAQR_SUCCESS;
 }
 
+// T of every leaf and node of panel idx (T_leaf / T_node already assigned).
+caqr_status_t launch_panel_t(caqr_handle_t h, caqr_factors_t F, int idx, hipStream_t st) {
+  const PanelRec &p = F->panels[idx];
+  FormTParams f;
+  f.Y = F->A + p.row0 + p.col0 * F->lda;
+  f.ldy = F->lda;
+  f.m = p.m;
+  f.b = p.b;
+  f.L = p.L;
+  f.h = F->leaf_rows;
+  f.tau_leaf = p.tau_leaf;
+  f.tau_node = p.tau_node;
+  f.T_leaf = p.T_leaf;
+  f.T_node = p.T_node;
+  TraceScope ts(h, CAQR_TRACE_FORM_T, idx, p.m, p.b, p.b, p.L, st);
+  return launch_form_t(f, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
+}
+
+// Factor panel idx (the tree climb), then, when asked, form its T factors on
+// the same stream.
 caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form_t, hipStream_t st) {
   const PanelRec &p = F->panels[idx];
   PanelParams pp = panel_params(h, F, p);
-  TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
-  return launch_tsqr_panel(pp, F->leaf_rows, form_t, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
+  {
+    TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
+    if (launch_tsqr_panel(pp, F->leaf_rows, st) != hipSuccess) return CAQR_ERR_DEVICE;
+  }
+  return form_t ? launch_panel_t(h, F, idx, st) : CAQR_SUCCESS;
 }
 
 // Q_idx^T applied to the columns [c0, c0 + k) of A (rows of the panel).
@@ -342,26 +363,17 @@ caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) 
 caqr_status_t ensure_t(caqr_handle_t h, caqr_factors_t F) {
   if (F->t_formed || F->panels.empty()) return CAQR_SUCCESS;
   if (F->limit && F->tbuf_bytes > F->limit) return CAQR_ERR_ALLOC;
-  if (hipMalloc(&F->tbuf, F->tbuf_bytes) != hipSuccess) return CAQR_ERR_ALLOC;
+  if (!F->tbuf && hipMalloc(&F->tbuf, F->tbuf_bytes) != hipSuccess) return CAQR_ERR_ALLOC;
   double *t = F->tbuf;
   for (auto &p : F->panels) {
     p.T_leaf = t;
     t += (size_t)p.L * kNbMax * kNbMax;
     p.T_node = t;
     t += (size_t)p.L * kNbMax * kNbMax;
-    FormTParams f;
-    f.Y = F->A + p.row0 + p.col0 * F->lda;
-    f.ldy = F->lda;
-    f.m = p.m;
-    f.b = p.b;
-    f.L = p.L;
-    f.h = F->leaf_rows;
-    f.tau_leaf = p.tau_leaf;
-    f.tau_node = p.tau_node;
-    f.T_leaf = p.T_leaf;
-    f.T_node = p.T_node;
-    TraceScope ts(h, CAQR_TRACE_FORM_T, (int)(&p - &F->panels[0]), p.m, p.b, p.b, p.L);
-    if (launch_form_t(f, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+  }
+  for (int idx = 0; idx < (int)F->panels.size(); ++idx) {
+    caqr_status_t st = launch_panel_t(h, F, idx, h->stream);
+    if (st) return st;
   }
   F->t_formed = true;
   return CAQR_SUCCESS;

@@ -19,8 +19,6 @@ struct PanelParams {
   int lpw;        // leaves per workgroup (1, 2, 4)
   double *tau_leaf;   // [L][64]
   double *tau_node;   // [L][64], node id = eliminated leaf (1..L-1)
-  double *T_leaf;     // [L][64*64] column-major, or null
-  double *T_node;     // [L][64*64], or null
   double *d;          // [64] signs of the root R
   unsigned *tickets;  // [L], zero on entry and on exit
 };
@@ -45,7 +43,7 @@ struct UpdateParams {
   int level;          // node kernels: tree level processed (half = 1 << (level-1))
 };
 
-hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, bool form_t, hipStream_t s);
+hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s);
 
 // C <- Q^T C for one panel: leaf updates and the tree bottom-up, then rows
 // 0..b-1 scaled by D.  One workgroup per (group of u.group leaves, tile) runs
@@ -57,7 +55,8 @@ hipError_t launch_apply_qt(const UpdateParams &u, hipStream_t s);
 // launch per level), then the leaves.
 hipError_t launch_apply_qn(const UpdateParams &u, hipStream_t s);
 
-// T factors of every leaf and node of a panel factored without them.
+// T factors (column-major 64x64, ld 64) of every leaf and node of a factored
+// panel; h must be a multiple of 16.
 struct FormTParams {
   const double *Y;  // panel origin
   int64_t ldy;

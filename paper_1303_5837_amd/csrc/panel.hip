@@ -24,29 +24,26 @@
 //
 // Outputs: R (b-by-b, non-negative diagonal) in the top rows of the panel; leaf
 // reflectors below each leaf's diagonal; each node's V (upper triangular) over
-// the eliminated child's R slot; tau per leaf/node; optionally T per leaf/node
-// (compact WY, Q = I - Y T Y^T); the signs D of the root R.
+// the eliminated child's R slot; tau per leaf/node; the signs D of the root R.
+// The compact-WY factors T (Q = I - Y T Y^T) of every leaf and node are formed
+// afterwards by one separate launch, all of them in parallel, so that the tree
+// climb (the critical path of the panel) carries no T work.
 #include <cfloat>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "tfactor.hpp"
 
 namespace caqr {
 
 namespace {
 
-constexpr int kLdG = kMaxB + 1;  // padded leading dimension of G and T in LDS
-
-template <bool FORM_T>
 struct PanelSmem {
   double v[2][16 * 16];  // Householder vector of the current step (by row), double-buffered
   double tau[2];
   double taus[kMaxB];
   double dsign[kMaxB];
   int flag;
-  double G[FORM_T ? kMaxB * kLdG : 1];  // strictly upper Y^T Y
-  double T[FORM_T ? kMaxB * kLdG : 1];  // T of the current factorization
-  double X[FORM_T ? 48 * 16 : 1];       // block product scratch of the T formation
 };
 
 // One Householder step per column j = 0..b-1 on the block held in a[][]:
@@ -56,8 +53,8 @@ struct PanelSmem {
 // tau = (beta - alpha) / beta, v = [1; x(2:) / (alpha - beta)]; x(2:) == 0 gives
 // tau = 0 (H = I).  The norm is an unscaled sum of squares, recomputed with
 // power-of-two scaling when alpha^2 + sigma is zero, subnormal or overflows.
-template <int NCH, int NQ, int NACT, bool STACK, bool FORM_T>
-__device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, PanelSmem<FORM_T> &sm) {
+template <int NCH, int NQ, int NACT, bool STACK>
+__device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, PanelSmem &sm) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int r = lane & 15;
@@ -154,8 +151,7 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
       __syncthreads();
       // ---- every thread: w = v^T A(:, col) for its column slots, then the rank-1 update.
       // v is read from LDS where it is used (not held across the reductions).
-      // Slots whose columns are all finished (q < Q) are skipped unless their
-      // dot products are needed for T (G = Y^T Y).
+      // Slots whose columns are all finished (q < Q) are skipped.
       const double tau = sm.tau[par];
       const double *vrow = sm.v[par] + r;
       double p[NQ];
@@ -168,19 +164,16 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
         const double vi = vrow[16 * i];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          if (!FORM_T && q < Q) continue;
+          if (q < Q) continue;
           p[q] = fma(vi, a[i][q], p[q]);
         }
       }
       double coef[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        if (!FORM_T && q < Q) continue;
+        if (q < Q) continue;
         const double w = row16_sum(p[q]);
         const int col = c + 16 * q;
-        if (FORM_T) {
-          if (r == 0 && col < j) sm.G[col * kLdG + j] = w;
-        }
         coef[q] = (col > j && col < b) ? tau * w : 0.0;
       }
 #pragma unroll
@@ -196,76 +189,6 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
       }
     }
   }
-}
-
-// T (upper triangular, Q = I - Y T Y^T) from G = strictly-upper(Y^T Y) and tau,
-// by the blocked forward recurrence: diagonal 16x16 blocks first
-// (T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j)), then each block
-// column bc: T(0:16bc, blk) = -T(0:16bc, 0:16bc) G(0:16bc, blk) T(blk, blk).
-// Result in sm.T (kLdG-strided, row-major by row index), zero outside 0..b-1.
-template <int NQ, bool FORM_T>
-__device__ __forceinline__ void form_t(int b, PanelSmem<FORM_T> &sm) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  // diagonal blocks: wave a handles block a, lanes 0..15 own one row each
-  if (wave < NQ && lane < 16) {
-    const int a0 = 16 * wave;
-    const int i = lane;
-    double t[16];
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      const int j = a0 + jj;
-      const double tj = (j < b) ? sm.taus[j] : 0.0;
-      double s = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < jj; ++kk) {
-        const double g = sm.G[(a0 + kk) * kLdG + j];
-        s = (kk >= i) ? fma(t[kk], g, s) : s;
-      }
-      t[jj] = (i < jj) ? -tj * s : ((i == jj) ? tj : 0.0);
-    }
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) sm.T[(a0 + i) * kLdG + a0 + jj] = t[jj];
-    // zero the strictly-lower part of this block row outside the diagonal block
-    for (int k = 0; k < a0; ++k) sm.T[(a0 + i) * kLdG + k] = 0.0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int bc = 1; bc < NQ; ++bc) {
-    const int c0 = 16 * bc;
-    // X = G(0:c0, c0:c0+16) * T(c0:c0+16, c0:c0+16)
-    for (int e = tid; e < c0 * 16; e += kThreads) {
-      const int i = e >> 4, jj = e & 15;
-      double s = 0.0;
-      for (int kk = 0; kk <= jj; ++kk) s = fma(sm.G[i * kLdG + c0 + kk], sm.T[(c0 + kk) * kLdG + c0 + jj], s);
-      sm.X[i * 16 + jj] = s;
-    }
-    __syncthreads();
-    // T(0:c0, c0:c0+16) = -T(0:c0, 0:c0) * X
-    for (int e = tid; e < c0 * 16; e += kThreads) {
-      const int i = e >> 4, jj = e & 15;
-      double s = 0.0;
-      for (int k = i; k < c0; ++k) s = fma(sm.T[i * kLdG + k], sm.X[k * 16 + jj], s);
-      sm.T[i * kLdG + c0 + jj] = -s;
-    }
-    __syncthreads();
-  }
-}
-
-// Write sm.T to global as a 64x64 column-major block (ld 64), zero outside b.
-template <bool FORM_T>
-__device__ __forceinline__ void store_t(double *Tg, int b, const PanelSmem<FORM_T> &sm) {
-  for (int e = threadIdx.x; e < kMaxB * kMaxB; e += kThreads) {
-    const int i = e & 63, j = e >> 6;
-    Tg[e] = (i <= j && j < b) ? sm.T[i * kLdG + j] : 0.0;
-  }
-}
-
-template <bool FORM_T>
-__device__ __forceinline__ void clear_g(PanelSmem<FORM_T> &sm) {
-  if (FORM_T)
-    for (int e = threadIdx.x; e < kMaxB * kLdG; e += kThreads) sm.G[e] = 0.0;
 }
 
 // Global element (row, col) of the panel, row within [0, m).
@@ -311,31 +234,25 @@ __device__ __forceinline__ void store_upper(const double (&a)[NCH][NQ], const Pa
 // Eliminate the R at slot `right` against the R at slot `left` (both read from
 // global).  Writes V over the right slot, tau/T of node `right`, and the new
 // R over the left slot.  The new R stays in chunks 0..NQ-1.
-template <int NCH, int NQ, bool FORM_T>
+template <int NCH, int NQ>
 __device__ __forceinline__ void combine(double (&a)[NCH][NQ], const PanelParams &p, int left, int right, int h,
-                        PanelSmem<FORM_T> &sm) {
+                                        PanelSmem &sm) {
   const int64_t lrow = (int64_t)left * h, rrow = (int64_t)right * h;
   load_r<NCH, NQ>(a, p, lrow, 0);
   load_r<NCH, NQ>(a, p, rrow, NQ);
-  clear_g(sm);
   __syncthreads();
-  householder_steps<NCH, NQ, 2 * NQ, true, FORM_T>(a, p.b, sm);
+  householder_steps<NCH, NQ, 2 * NQ, true>(a, p.b, sm);
   store_upper<NCH, NQ>(a, p, rrow, NQ);  // V of the node
   store_upper<NCH, NQ>(a, p, lrow, 0);   // R of the survivor
   __syncthreads();
   if (threadIdx.x < kMaxB) p.tau_node[(int64_t)right * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : 0.0;
-  if (FORM_T) {
-    form_t<NQ, FORM_T>(p.b, sm);
-    store_t(p.T_node + (int64_t)right * kMaxB * kMaxB, p.b, sm);
-  }
   __syncthreads();
 }
 
 // Last-arriver ticket on node `node`; true when this workgroup arrived second
 // (and must perform the elimination).  Publishes this workgroup's prior global
 // stores before the ticket and acquires the partner's after it.
-template <bool FORM_T>
-__device__ __forceinline__ bool arrive(const PanelParams &p, int node, PanelSmem<FORM_T> &sm) {
+__device__ __forceinline__ bool arrive(const PanelParams &p, int node, PanelSmem &sm) {
   fence_release();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -349,11 +266,11 @@ __device__ __forceinline__ bool arrive(const PanelParams &p, int node, PanelSmem
   return second;
 }
 
-template <int RPT, int NQ, bool FORM_T>
+template <int RPT, int NQ>
 __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) {
   constexpr int NCH = (RPT > 2 * NQ) ? RPT : 2 * NQ;
   constexpr int H = 16 * RPT;
-  __shared__ PanelSmem<FORM_T> sm;
+  __shared__ PanelSmem sm;
   double a[NCH][NQ];
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
@@ -384,9 +301,8 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) 
           a[i][q] = (i < RPT && grow < p.m && col < p.b) ? *pan(p, grow, col) : 0.0;
         }
     }
-    clear_g(sm);
     __syncthreads();
-    householder_steps<NCH, NQ, RPT, false, FORM_T>(a, p.b, sm);
+    householder_steps<NCH, NQ, RPT, false>(a, p.b, sm);
     if (full) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -407,10 +323,6 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) 
     __syncthreads();
     if (threadIdx.x < kMaxB)
       p.tau_leaf[(int64_t)leaf * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : 0.0;
-    if (FORM_T) {
-      form_t<NQ, FORM_T>(p.b, sm);
-      store_t(p.T_leaf + (int64_t)leaf * kMaxB * kMaxB, p.b, sm);
-    }
     __syncthreads();
 
     // ---- levels 2 and 3: climb the binary tree from this leaf
@@ -425,13 +337,13 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) 
           break;
         }
         if (!arrive(p, partner, sm)) return;         // the sibling's workgroup finishes the node
-        combine<NCH, NQ, FORM_T>(a, p, rt, partner, H, sm);
+        combine<NCH, NQ>(a, p, rt, partner, H, sm);
       } else {  // right child: node id rt, left sibling rt - half
         const int left = rt - half;
         if (left < leaf0) {
           if (!arrive(p, rt, sm)) return;
         }
-        combine<NCH, NQ, FORM_T>(a, p, left, rt, H, sm);
+        combine<NCH, NQ>(a, p, left, rt, H, sm);
         rt = left;
       }
     }
@@ -457,42 +369,43 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) 
   }
 }
 
-template <int RPT, int NQ, bool FORM_T>
+
+template <int RPT, int NQ>
 hipError_t launch_panel_t(const PanelParams &p, hipStream_t s) {
   const int grid = (p.L + p.lpw - 1) / p.lpw;
-  hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ, FORM_T>), dim3(grid), dim3(kThreads), 0, s, p);
+  hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ>), dim3(grid), dim3(kThreads), 0, s, p);
   return hipGetLastError();
 }
 
-template <int RPT, bool FORM_T>
+template <int RPT>
 hipError_t launch_panel_nq(const PanelParams &p, hipStream_t s) {
   switch ((p.b + 15) / 16) {
-    case 1: return launch_panel_t<RPT, 1, FORM_T>(p, s);
-    case 2: return launch_panel_t<RPT, 2, FORM_T>(p, s);
-    case 3: return launch_panel_t<RPT, 3, FORM_T>(p, s);
-    case 4: return launch_panel_t<RPT, 4, FORM_T>(p, s);
+    case 1: return launch_panel_t<RPT, 1>(p, s);
+    case 2: return launch_panel_t<RPT, 2>(p, s);
+    case 3: return launch_panel_t<RPT, 3>(p, s);
+    case 4: return launch_panel_t<RPT, 4>(p, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <bool FORM_T>
-hipError_t launch_panel_rpt(const PanelParams &p, int leaf_rows, hipStream_t s) {
-  switch (leaf_rows) {
-    case 64: return launch_panel_nq<4, FORM_T>(p, s);
-    case 128: return launch_panel_nq<8, FORM_T>(p, s);
-    case 256: return launch_panel_nq<16, FORM_T>(p, s);
-    default: return hipErrorInvalidValue;
-  }
-}
+constexpr int kLdG = kMaxB + 1;  // padded leading dimension of G and T in LDS
 
-// T of one leaf (blockIdx.x < L) or node (blockIdx.x = L + node id) of a panel
-// that was factored without T.  G = strictly-upper(Y^T Y) is computed on FP64
-// MFMA (leaf: Y unit lower trapezoidal, h rows; node: [I; V], whose identity
-// part contributes nothing off the diagonal), then T by the same blocked
-// recurrence as in the panel kernel.
+struct TSmem {
+  double G[kMaxB * kLdG];  // strictly upper Y^T Y
+  double T[kMaxB * kLdG];
+  double taus[kMaxB];
+};
+
+// T of one leaf (blockIdx.x < L) or tree node (blockIdx.x = L + node id) of a
+// factored panel; all leaves and nodes of the panel are independent, so they
+// run in one launch.  G = Y^T Y on FP64 MFMA: each wave accumulates every
+// 16x16 block on or above the diagonal over a quarter of the rows (leaf: Y
+// unit lower trapezoidal, h rows; node: [I; V] with V upper triangular, whose
+// identity part adds nothing off the diagonal), the four partial sums are
+// added in LDS in wave order, then T follows from G and tau.
 template <int NQ>
 __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
-  __shared__ PanelSmem<true> sm;
+  __shared__ TSmem sm;
   const bool is_leaf = (int)blockIdx.x < f.L;
   const int idx = is_leaf ? (int)blockIdx.x : (int)blockIdx.x - f.L;
   if (!is_leaf && idx == 0) return;
@@ -500,44 +413,56 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
   const int wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t row0 = (int64_t)idx * f.h;
-  const int rows = is_leaf ? f.h : 16 * NQ;
-  for (int e = threadIdx.x; e < kMaxB * kLdG; e += kThreads) sm.G[e] = 0.0;
+  const int rows = is_leaf ? f.h : 16 * NQ;  // a multiple of 16
+  const int per = rows / 4;                    // rows of each wave, a multiple of 4
   if (threadIdx.x < kMaxB) {
     const double *tau = is_leaf ? f.tau_leaf : f.tau_node;
     sm.taus[threadIdx.x] = (threadIdx.x < f.b) ? tau[(int64_t)idx * kMaxB + threadIdx.x] : 0.0;
   }
-  __syncthreads();
-  if (wave < NQ) {
-    f64x4 g[NQ];
+  f64x4 g[NQ][NQ];
 #pragma unroll
-    for (int a = 0; a < NQ; ++a) g[a] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int s = 0; s < rows / 4; ++s) {
-      const int row = 4 * s + lk;
-      const int64_t grow = row0 + row;
-      // reflector entry (row, col) of this leaf/node
-      auto refl = [&](int col) -> double {
-        if (col >= f.b) return 0.0;
-        if (is_leaf) {
-          if (row == col) return 1.0;
-          return (row > col && grow < f.m) ? f.Y[grow + (int64_t)col * f.ldy] : 0.0;
-        }
-        return (row <= col && grow < f.m) ? f.Y[grow + (int64_t)col * f.ldy] : 0.0;
-      };
-      const double av = refl(16 * wave + li);
+  for (int a = 0; a < NQ; ++a)
 #pragma unroll
-      for (int a = 0; a < NQ; ++a) g[a] = mfma16x16x4(av, refl(16 * a + li), g[a]);
+    for (int c = 0; c < NQ; ++c) g[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < per; s += 4) {
+    const int row = wave * per + s + lk;
+    const int64_t grow = row0 + row;
+    double y[NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+      const int col = 16 * a + li;
+      double e = 0.0;
+      if (col < f.b && grow < f.m) {
+        if (is_leaf)
+          e = (row == col) ? 1.0 : ((row > col) ? f.Y[grow + (int64_t)col * f.ldy] : 0.0);
+        else
+          e = (row <= col) ? f.Y[grow + (int64_t)col * f.ldy] : 0.0;
+      }
+      y[a] = e;
     }
 #pragma unroll
     for (int a = 0; a < NQ; ++a)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * wave + 4 * r + lk, k = 16 * a + li;
-        if (i < k) sm.G[i * kLdG + k] = g[a][r];
-      }
+      for (int c = a; c < NQ; ++c) g[a][c] = mfma16x16x4(y[a], y[c], g[a][c]);
   }
-  __syncthreads();
-  form_t<NQ, true>(f.b, sm);
-  store_t(is_leaf ? f.T_leaf + (int64_t)idx * kMaxB * kMaxB : f.T_node + (int64_t)idx * kMaxB * kMaxB, f.b, sm);
+  // G(16a + i, 16c + j), i = 4 r + lk, j = li, in register r of block (a, c)
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int a = 0; a < NQ; ++a)
+#pragma unroll
+        for (int c = a; c < NQ; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * a + 4 * r + lk, k = 16 * c + li;
+            if (i < k) sm.G[i * kLdG + k] = (w == 0) ? g[a][c][r] : sm.G[i * kLdG + k] + g[a][c][r];
+          }
+    }
+    __syncthreads();
+  }
+  form_t_lds<NQ>(f.b, sm.G, sm.T, sm.taus, kLdG);
+  store_t_global(is_leaf ? f.T_leaf + (int64_t)idx * kMaxB * kMaxB : f.T_node + (int64_t)idx * kMaxB * kMaxB, f.b,
+                 sm.T, kLdG);
 }
 
 template <int NQ>
@@ -548,17 +473,18 @@ hipError_t launch_form_t_nq(const FormTParams &f, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, bool form_t, hipStream_t s) {
+hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s) {
   if (p.b < 1 || p.b > kMaxB || p.L < 1 || p.lpw < 1) return hipErrorInvalidValue;
-  return form_t ? launch_panel_rpt<true>(p, leaf_rows, s) : launch_panel_rpt<false>(p, leaf_rows, s);
+  switch (leaf_rows) {
+    case 64: return launch_panel_nq<4>(p, s);
+    case 128: return launch_panel_nq<8>(p, s);
+    case 256: return launch_panel_nq<16>(p, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-}  // namespace caqr
-
-namespace caqr {
-
 hipError_t launch_form_t(const FormTParams &f, hipStream_t s) {
-  if (f.b < 1 || f.b > kMaxB || f.L < 1) return hipErrorInvalidValue;
+  if (f.b < 1 || f.b > kMaxB || f.L < 1 || f.h % 16 != 0) return hipErrorInvalidValue;
   switch ((f.b + 15) / 16) {
     case 1: return launch_form_t_nq<1>(f, s);
     case 2: return launch_form_t_nq<2>(f, s);
