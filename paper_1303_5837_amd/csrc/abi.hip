@@ -266,9 +266,9 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
   u.d = p.d;
   u.tiles = ceil_div(k, kUpdTile);
   // leaves per workgroup: the smallest power of two that keeps the grid
-  // within about four workgroups per CU slot pair (256 CUs x 2 slots x 2)
+  // within about two workgroups per CU (one resident at a time, 256 CUs)
   int g = 1;
-  while (g < p.L && (int64_t)ceil_div(p.L, g) * u.tiles > 1024) g <<= 1;
+  while (g < p.L && (int64_t)ceil_div(p.L, g) * u.tiles > 512) g <<= 1;
   u.group = g;
   u.level = 0;
   return u;

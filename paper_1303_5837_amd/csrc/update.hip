@@ -11,14 +11,15 @@
 //   node   (top b rows of the two leaves): W = C_1 + V^T C_2,  W <- T^T W,
 //                                          C_1 -= W,  C_2 -= V W
 //
-// (T instead of T^T for Q C.)  One workgroup updates one leaf's rows of one
-// 64-column tile; wave w owns columns 16w..16w+15 of the tile and keeps them in
-// registers between the two products, so C is read and written once.  The
-// reflectors are staged through LDS in 64x64 blocks (double-buffered, loaded
-// with coalesced 16-byte accesses), and T goes through the same buffers.  For
-// Q^T the tree levels follow in the same launch: per (node, tile) an
-// agent-scope ticket lets the second workgroup to finish below a node perform
-// that node's update on the tile.
+// (T instead of T^T for Q C.)  One workgroup updates the rows of a group of
+// leaves on one 64-column tile; wave w owns columns 16w..16w+15 of the tile
+// over all rows of a leaf and keeps them in registers between the two
+// products, so C is read and written once per leaf and no partial sums cross
+// waves.  The reflectors are staged through LDS in 64x64 blocks
+// (double-buffered, loaded with coalesced 16-byte accesses), and T goes
+// through the same buffers.  For Q^T the tree levels that lie inside a group
+// follow in the same launch; the levels above the groups run one launch per
+// level, so no workgroup ever waits for another.
 //
 // Register layout ("contiguous"): a 16-row slab x of a tile is an f64x4 per
 // lane holding rows 16x + 4*(lane/16) + r, r = 0..3, of column lane%16.  The
@@ -45,15 +46,6 @@ __device__ __forceinline__ int pi16(int li) { return 4 * (li & 3) + (li >> 2); }
 
 __device__ __forceinline__ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
-// The thread index passed through a register move the compiler cannot see
-// through: computations derived from it inside a loop body are redone per
-// iteration instead of being hoisted (and kept live) across the whole loop.
-__device__ __forceinline__ int opaque_tid() {
-  int t;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
-  return t;
-}
-
 enum BlockKind { kLeafY = 0, kNodeV = 1, kDense = 2 };
 
 // A 64x64 block staged through registers: thread tid holds 8 row pairs.
@@ -62,16 +54,15 @@ struct Stage {
   f64x2 v[8];
 };
 
-// Load a 64x64 block of reflectors (or T) from global memory into registers.
-// Block rows 0..31 are source rows src0 + 0..31 and block rows 32..63 are
-// source rows src1 + 0..31 (rows relative to the panel; src0 + 32 == src1 for a
-// contiguous block).  For KIND kLeafY, `lr_off` converts a panel row to the row
-// within the leaf (lr = row - lr_off), and the value is the unit
-// lower-trapezoidal leaf reflector; kNodeV: the upper-triangular V whose row 0
-// is panel row lr_off; kDense: a dense 64x64 column-major block, ld 64 (T).
+// Load a 64x64 block of reflectors (or T) from global memory into registers:
+// block rows 0..63 are the panel rows src0..src0+63.  For KIND kLeafY, `lr_off`
+// converts a panel row to the row within the leaf (lr = row - lr_off) and the
+// value is the unit lower-trapezoidal leaf reflector; kNodeV: the upper
+// triangular V whose row 0 is panel row lr_off; kDense: a dense 64x64
+// column-major block, ld 64 (T).
 template <int KIND>
-__device__ __forceinline__ void stage_load(Stage &st, const double *base, int64_t ld, int64_t src0, int64_t src1,
-                                           int64_t lr_off, int64_t m, int b, bool vec_ok, int tid) {
+__device__ __forceinline__ void stage_load(Stage &st, const double *base, int64_t ld, int64_t src0, int64_t lr_off,
+                                           int64_t m, int b, bool vec_ok, int tid) {
   const int row = 2 * (tid & 31);  // block row pair of this thread (same for every s)
   const int colt = tid >> 5;       // block column for s = 0; s adds 8
   if (KIND == kDense) {
@@ -79,10 +70,10 @@ __device__ __forceinline__ void stage_load(Stage &st, const double *base, int64_
     for (int s = 0; s < 8; ++s) st.v[s] = *reinterpret_cast<const f64x2 *>(base + row + 64 * (colt + 8 * s));
     return;
   }
-  const int64_t g0 = (row < 32) ? src0 + row : src1 + (row - 32);
+  const int64_t g0 = src0 + row;
   const int64_t lr = g0 - lr_off;
   // uniform fast path: full-width panel, every row in range, 16-byte aligned
-  const bool fast = vec_ok && b == kMaxB && src0 + 31 < m && src1 + 31 < m;
+  const bool fast = vec_ok && b == kMaxB && src0 + 63 < m;
   if (fast) {
     const double *p = base + g0 + (int64_t)colt * ld;
 #pragma unroll
@@ -190,105 +181,71 @@ __device__ __forceinline__ void apply_t_lds(const double *Ts, f64x4 (&w)[NQ]) {
   }
 }
 
-// The two waves of a column group hold partial sums of W over the two row
-// halves; after this call both hold W = P(half 0) + P(half 1) (same order in
-// both, so the two copies are bitwise equal).  `xbuf` is a free LDS block.
-template <int NQ>
-__device__ __forceinline__ void exchange_w(f64x4 (&w)[NQ], double *xbuf) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int cg = wave & 1, rh = wave >> 1;
-  f64x4 *x = reinterpret_cast<f64x4 *>(xbuf);
-#pragma unroll
-  for (int a = 0; a < NQ; ++a) x[((cg * 2 + rh) * NQ + a) * 64 + lane] = w[a];
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < NQ; ++a) {
-    const f64x4 p0 = x[((cg * 2 + 0) * NQ + a) * 64 + lane];
-    const f64x4 p1 = x[((cg * 2 + 1) * NQ + a) * 64 + lane];
-    w[a] = p0 + p1;
-  }
-}
-
 // Update of the top b rows of tree node `node` (eliminated leaf) and of its
-// left sibling on this workgroup's tile.  Wave (cg, rh) holds rows
-// 32rh..32rh+31 of both row blocks for columns 16cg..16cg+15; the two waves of
-// a column group form W = C1 + V^T C2 from partial sums over their rows.
+// left sibling on this workgroup's tile.  Wave w holds all 16*NQ top rows of
+// both row blocks for columns 16w..16w+15, so W = C1 + V^T C2 is complete in
+// every wave.  V goes to LDS buffer 0 and T to buffer 1.
 template <int NQ, bool TRANS>
 __device__ __forceinline__ void node_update(const UpdateParams &u, int left, int node, int tile, UpdSmem &sm,
                                             bool vec_ok) {
-  constexpr int NS = 2;  // 16-row slabs per wave: slab t = 2 rh + x
-  const int tid = opaque_tid();
+  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int cg = wave & 1, rh = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
   const int pl = pi16(li);
-  const int64_t col = (int64_t)tile * kUpdTile + 16 * cg + li;
+  const int64_t col = (int64_t)tile * kUpdTile + 16 * wave + li;
   const bool colok = col < u.k;
   const int64_t r1 = (int64_t)left * u.h, r2 = (int64_t)node * u.h;
   const int64_t m1 = min<int64_t>(u.m, r1 + u.b), m2 = min<int64_t>(u.m, r2 + u.b);
   Stage st;
-  stage_load<kNodeV>(st, u.Y, u.ldy, r2, r2 + 32, r2, u.m, u.b, vec_ok, tid);
+  stage_load<kNodeV>(st, u.Y, u.ldy, r2, r2, u.m, u.b, vec_ok, tid);
   stage_store(st, sm.buf[0], tid);
-  stage_load<kDense>(st, u.T_node + (int64_t)node * 64 * 64, 64, 0, 0, 0, 0, 0, true, tid);
-  f64x4 c1[NS], c2[NS];
+  stage_load<kDense>(st, u.T_node + (int64_t)node * 64 * 64, 64, 0, 0, 0, 0, true, tid);
+  stage_store(st, sm.buf[1], tid);
+  f64x4 c1[NQ], c2[NQ];
 #pragma unroll
-  for (int x = 0; x < NS; ++x) {
-    c1[x] = load_slab(u.C, u.ldc, r1 + 32 * rh + 16 * x + 4 * lk, col, m1, colok, vec_ok);
-    c2[x] = load_slab(u.C, u.ldc, r2 + 32 * rh + 16 * x + 4 * lk, col, m2, colok, vec_ok);
+  for (int t = 0; t < NQ; ++t) {
+    c1[t] = load_slab(u.C, u.ldc, r1 + 16 * t + 4 * lk, col, m1, colok, vec_ok);
+    c2[t] = load_slab(u.C, u.ldc, r2 + 16 * t + 4 * lk, col, m2, colok, vec_ok);
   }
   __syncthreads();
-  // partial W over this wave's rows: own slabs of C1 plus V(rows)^T C2(rows)
+  // W = C1 + V^T C2 (V upper triangular: slab t reaches blocks a >= t)
   f64x4 w[NQ];
 #pragma unroll
   for (int a = 0; a < NQ; ++a) {
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    f64x4 acc = c1[a];
 #pragma unroll
-    for (int x = 0; x < NS; ++x) {
-      const int t = 2 * rh + x;
-      if (t > a) continue;  // V upper triangular
+    for (int t = 0; t <= a; ++t) {
       const f64x4 v = lds_col4(sm.buf[0], 16 * a + pl, 16 * t + 4 * lk);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc = mfma16x16x4(v[r], c2[x][r], acc);
+      for (int r = 0; r < 4; ++r) acc = mfma16x16x4(v[r], c2[t][r], acc);
     }
-#pragma unroll
-    for (int x = 0; x < NS; ++x)
-      if (2 * rh + x == a) acc += c1[x];
     w[a] = acc;
   }
-  exchange_w<NQ>(w, sm.buf[1]);
-  __syncthreads();
-  stage_store(st, sm.buf[1], tid);  // T
-  __syncthreads();
   apply_t_lds<NQ, TRANS>(sm.buf[1], w);
-  f64x4 (&w2)[NQ] = w;
-  // C1 -= W' (own slabs);  C2 -= V W' (own rows)
+  // C1 -= W';  C2 -= V W'
 #pragma unroll
-  for (int x = 0; x < NS; ++x) {
-    const int t = 2 * rh + x;
+  for (int t = 0; t < NQ; ++t) {
+    c1[t] -= w[t];
+    f64x4 acc = c2[t];
 #pragma unroll
-    for (int a = 0; a < NQ; ++a)
-      if (a == t) c1[x] -= w2[a];
-    f64x4 acc = c2[x];
-#pragma unroll
-    for (int a = 0; a < NQ; ++a) {
-      if (a < t) continue;
+    for (int a = t; a < NQ; ++a) {
       const f64x4 v = lds_row4(sm.buf[0], 16 * t + pl, 16 * a + 4 * lk);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc = mfma16x16x4(-v[r], w2[a][r], acc);
+      for (int r = 0; r < 4; ++r) acc = mfma16x16x4(-v[r], w[a][r], acc);
     }
-    c2[x] = acc;
+    c2[t] = acc;
   }
 #pragma unroll
-  for (int x = 0; x < NS; ++x) {
-    store_slab(u.C, u.ldc, r1 + 32 * rh + 16 * x + 4 * lk, col, m1, colok, vec_ok, c1[x]);
-    store_slab(u.C, u.ldc, r2 + 32 * rh + 16 * x + 4 * lk, col, m2, colok, vec_ok, c2[x]);
+  for (int t = 0; t < NQ; ++t) {
+    store_slab(u.C, u.ldc, r1 + 16 * t + 4 * lk, col, m1, colok, vec_ok, c1[t]);
+    store_slab(u.C, u.ldc, r2 + 16 * t + 4 * lk, col, m2, colok, vec_ok, c2[t]);
   }
   __syncthreads();  // LDS buffers free again
 }
 
-// Rows 0..b-1 of this workgroup's tile scaled by D.
+// Rows 0..b-1 of this workgroup's tile scaled by D (any thread mapping; the
+// caller orders it after the tile's last update).
 __device__ __forceinline__ void scale_top_rows(const UpdateParams &u, int tile) {
   for (int e = threadIdx.x; e < u.b * kUpdTile; e += kThreads) {
     const int row = e % u.b;
@@ -297,68 +254,84 @@ __device__ __forceinline__ void scale_top_rows(const UpdateParams &u, int tile) 
   }
 }
 
-// Q^T update of one leaf on one tile: C_leaf <- C_leaf - Y (T^T (Y^T C_leaf)).
-// Wave (cg, rh) holds rows rh*H/2 .. rh*H/2 + H/2 - 1 of the leaf for columns
-// 16cg..16cg+15.  Reflector chunks hold 32 rows of each half (block rows
-// 0..31: half 0, 32..63: half 1), so every wave works on every chunk.
+// Rows 0..b-1 scaled by D, each lane on the rows it wrote itself in
+// node_update / leaf_update (rows 16t + 4(lane/16) + r of column lane%16).
+template <int NQ>
+__device__ __forceinline__ void scale_top_rows_own(const UpdateParams &u, int tile) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t col = (int64_t)tile * kUpdTile + 16 * wave + li;
+  if (col >= u.k) return;
+#pragma unroll
+  for (int t = 0; t < NQ; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + 4 * lk + r;
+      if (row < u.b && row < u.m) u.C[row + col * u.ldc] *= u.d[row];
+    }
+}
+
+// Q^T (TRANS) or Q update of one leaf on one tile: C_leaf <- C_leaf - Y (T^T (Y^T C_leaf)).
+// Wave w holds all H rows of the leaf for columns 16w..16w+15 in registers
+// (RT slabs of 16 rows), so both products are complete inside the wave.  The
+// reflectors go through LDS in 64-row chunks, double-buffered: chunks 0..n-1
+// for W = Y^T C, then T, then chunks n-1..0 for C -= Y W' (the last chunk of
+// the first pass is still in LDS and is not reloaded).  Chunk c always sits in
+// buffer c % 2; T sits in buffer n % 2.
 template <int NQ, int RT, bool TRANS>
 __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int tile, UpdSmem &sm) {
   constexpr int H = 16 * RT;       // leaf rows
-  constexpr int HALF = H / 2;      // rows per wave
-  constexpr int NX = RT / 2;       // 16-row slabs per wave
-  constexpr int NCHUNK = HALF / 32;
-  const int tid = opaque_tid();
+  constexpr int NCHUNK = H / 64;   // 64-row chunks
+  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int cg = wave & 1, rh = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
   const int pl = pi16(li);
   const int64_t row0 = (int64_t)leaf * u.h;
-  const int64_t col = (int64_t)tile * kUpdTile + 16 * cg + li;
+  const int64_t col = (int64_t)tile * kUpdTile + 16 * wave + li;
   const bool colok = col < u.k;
   const bool vec_c = aligned16(u.C) && (u.ldc % 2 == 0);
   const bool vec_y = aligned16(u.Y) && (u.ldy % 2 == 0);
 
   Stage st;
-  stage_load<kLeafY>(st, u.Y, u.ldy, row0, row0 + HALF, row0, u.m, u.b, vec_y, tid);
+  stage_load<kLeafY>(st, u.Y, u.ldy, row0, row0, u.m, u.b, vec_y, tid);
   // uniform fast path for C: the whole leaf x tile block in range and aligned
   const bool cfast = vec_c && row0 + H <= u.m && (int64_t)(tile + 1) * kUpdTile <= u.k;
-  double *cptr = u.C + row0 + rh * HALF + 4 * lk + col * u.ldc;
-  f64x4 acc[NX];  // rows row0 + rh*HALF + 16x + 4lk + r
+  double *cptr = u.C + row0 + 4 * lk + col * u.ldc;
+  f64x4 acc[RT];  // rows row0 + 16x + 4lk + r
   if (cfast) {
 #pragma unroll
-    for (int x = 0; x < NX; ++x) {
+    for (int x = 0; x < RT; ++x) {
       const f64x2 lo = *reinterpret_cast<const f64x2 *>(cptr + 16 * x);
       const f64x2 hi = *reinterpret_cast<const f64x2 *>(cptr + 16 * x + 2);
       acc[x] = f64x4{lo.x, lo.y, hi.x, hi.y};
     }
   } else {
 #pragma unroll
-    for (int x = 0; x < NX; ++x)
-      acc[x] = load_slab(u.C, u.ldc, row0 + rh * HALF + 16 * x + 4 * lk, col, u.m, colok, vec_c);
+    for (int x = 0; x < RT; ++x) acc[x] = load_slab(u.C, u.ldc, row0 + 16 * x + 4 * lk, col, u.m, colok, vec_c);
   }
   stage_store(st, sm.buf[0], tid);
   __syncthreads();
 
-  // ---- partial W = Y^T C over this wave's rows, chunk by chunk
+  // ---- W = Y^T C, chunk by chunk
   f64x4 w[NQ];
 #pragma unroll
   for (int a = 0; a < NQ; ++a) w[a] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < NCHUNK; ++c) {
     if (c + 1 < NCHUNK)
-      stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 32 * (c + 1), row0 + HALF + 32 * (c + 1), row0, u.m, u.b, vec_y, tid);
+      stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (c + 1), row0, u.m, u.b, vec_y, tid);
     else
-      stage_load<kDense>(st, u.T_leaf + (int64_t)leaf * 64 * 64, 64, 0, 0, 0, 0, 0, true, tid);
+      stage_load<kDense>(st, u.T_leaf + (int64_t)leaf * 64 * 64, 64, 0, 0, 0, 0, true, tid);
     const double *ys = sm.buf[c & 1];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int x = 2 * c + tt;
-      const int t = rh * NX + x;  // slab index within the leaf
+    for (int tt = 0; tt < 4; ++tt) {
+      const int x = 4 * c + tt;  // slab index within the leaf
 #pragma unroll
       for (int a = 0; a < NQ; ++a) {
-        if (t < a) continue;  // slab rows lie above the reflectors of block a
-        const f64x4 y = lds_col4(ys, 16 * a + pl, 32 * rh + 16 * tt + 4 * lk);
+        if (x < a) continue;  // slab rows lie above the reflectors of block a
+        const f64x4 y = lds_col4(ys, 16 * a + pl, 16 * tt + 4 * lk);
 #pragma unroll
         for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(y[r], acc[x][r], w[a]);
       }
@@ -366,78 +339,71 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
     stage_store(st, sm.buf[(c + 1) & 1], tid);
     __syncthreads();
   }
-  // ---- W = partial(half 0) + partial(half 1);  W' = T^T W (T in buf[NCHUNK & 1])
-  stage_load<kLeafY>(st, u.Y, u.ldy, row0, row0 + HALF, row0, u.m, u.b, vec_y, tid);
-  exchange_w<NQ>(w, sm.buf[(NCHUNK + 1) & 1]);
+  // ---- W' = T^T W (T in buffer NCHUNK % 2); the next chunk of the second
+  // pass (NCHUNK - 2) is loaded meanwhile and goes into T's buffer afterwards
+  if (NCHUNK > 1) stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (NCHUNK - 2), row0, u.m, u.b, vec_y, tid);
   apply_t_lds<NQ, TRANS>(sm.buf[NCHUNK & 1], w);
-  f64x4 (&w2)[NQ] = w;
   __syncthreads();
-  stage_store(st, sm.buf[0], tid);
-  __syncthreads();
-  // ---- C -= Y W', chunk by chunk
+  // ---- C -= Y W', chunks NCHUNK-1 .. 0
 #pragma unroll
-  for (int c = 0; c < NCHUNK; ++c) {
-    if (c + 1 < NCHUNK)
-      stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 32 * (c + 1), row0 + HALF + 32 * (c + 1), row0, u.m, u.b, vec_y, tid);
+  for (int c = NCHUNK - 1; c >= 0; --c) {
+    if (c >= 1) {
+      stage_store(st, sm.buf[(c - 1) & 1], tid);  // chunk c - 1 into the buffer chunk c + 1 (or T) left
+      if (c >= 2) stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (c - 2), row0, u.m, u.b, vec_y, tid);
+    }
     const double *ys = sm.buf[c & 1];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int x = 2 * c + tt;
-      const int t = rh * NX + x;
+    for (int tt = 0; tt < 4; ++tt) {
+      const int x = 4 * c + tt;
 #pragma unroll
       for (int a = 0; a < NQ; ++a) {
-        if (t < a) continue;
-        const f64x4 y = lds_row4(ys, 32 * rh + 16 * tt + pl, 16 * a + 4 * lk);
+        if (x < a) continue;
+        const f64x4 y = lds_row4(ys, 16 * tt + pl, 16 * a + 4 * lk);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(-y[r], w2[a][r], acc[x]);
+        for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(-y[r], w[a][r], acc[x]);
       }
     }
-    if (c + 1 < NCHUNK) {
-      stage_store(st, sm.buf[(c + 1) & 1], tid);
-      __syncthreads();
-    }
+    if (c >= 1) __syncthreads();
   }
   if (cfast) {
 #pragma unroll
-    for (int x = 0; x < NX; ++x) {
+    for (int x = 0; x < RT; ++x) {
       *reinterpret_cast<f64x2 *>(cptr + 16 * x) = f64x2{acc[x][0], acc[x][1]};
       *reinterpret_cast<f64x2 *>(cptr + 16 * x + 2) = f64x2{acc[x][2], acc[x][3]};
     }
   } else {
 #pragma unroll
-    for (int x = 0; x < NX; ++x)
-      store_slab(u.C, u.ldc, row0 + rh * HALF + 16 * x + 4 * lk, col, u.m, colok, vec_c, acc[x]);
+    for (int x = 0; x < RT; ++x) store_slab(u.C, u.ldc, row0 + 16 * x + 4 * lk, col, u.m, colok, vec_c, acc[x]);
   }
-  __syncthreads();  // C rows visible to the whole workgroup; LDS free
+  __syncthreads();  // LDS free for the next update
 }
 
 // Q^T of one panel on one tile, for the leaves of group g (u.group leaves,
-// a power of two): every leaf update, each followed by the tree levels that
-// become complete inside the group (binary pairs i, i + 2^(k-1), the lower
-// index on top).  A single group covers the whole tree and also applies D.
-// No workgroup depends on another, so no device-scope synchronization is
-// needed; the levels above the groups run afterwards, one launch per level.
+// a power of two): every leaf update, then the tree levels that are complete
+// inside the group (binary pairs i, i + 2^(k-1), the lower index on top).  A
+// single group covers the whole tree and also applies D.  No workgroup
+// depends on another, so no device-scope synchronization is needed; the
+// levels above the groups run afterwards, one launch per level.
 template <int NQ, int RT>
-__global__ void __launch_bounds__(kThreads, 2) qt_group_kernel(UpdateParams u) {
+__global__ void __launch_bounds__(kThreads, 1) qt_group_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
   const int ngroups = (u.L + u.group - 1) / u.group;
   const int g = blockIdx.x % ngroups;
   const int tile = blockIdx.x / ngroups;
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
   const int first = g * u.group, last = min(u.L, first + u.group);
-  // all leaves of the group, then the tree levels inside the group bottom-up
 #pragma nounroll
   for (int leaf = first; leaf < last; ++leaf) leaf_update<NQ, RT, true>(u, __builtin_amdgcn_readfirstlane(leaf), tile, sm);
   for (int half = 1; half < u.group && half < u.L; half <<= 1)
 #pragma nounroll
     for (int node = first + half; node < last; node += 2 * half)
       node_update<NQ, true>(u, node - half, node, tile, sm, vec_ok);
-  if (ngroups == 1) scale_top_rows(u, tile);
+  if (ngroups == 1) scale_top_rows_own<NQ>(u, tile);
 }
 
 // Q applied (not transposed): leaves only, no tree (the tree runs first, top-down).
 template <int NQ, int RT>
-__global__ void __launch_bounds__(kThreads, 2) qn_leaf_kernel(UpdateParams u) {
+__global__ void __launch_bounds__(kThreads, 1) qn_leaf_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
   const int leaf = blockIdx.x % u.L;
   const int tile = blockIdx.x / u.L;
