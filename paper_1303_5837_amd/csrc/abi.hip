@@ -271,6 +271,7 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
   while (g < p.L && (int64_t)ceil_div(p.L, g) * u.tiles > 512) g <<= 1;
   u.group = g;
   u.level = 0;
+  u.tickets = nullptr;
   return u;
 }
 
@@ -317,19 +318,24 @@ caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form
 }
 
 // Q_idx^T applied to the columns [c0, c0 + k) of A (rows of the panel).
-caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_t c0, int64_t k) {
+caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_t c0, int64_t k, hipStream_t st) {
   const PanelRec &p = F->panels[idx];
   UpdateParams u = update_params(h, F, p, F->A + c0 * F->lda, F->lda, k);
-  TraceScope ts(h, CAQR_TRACE_UPDATE_T, idx, p.m, k, p.b, p.L);
-  return launch_apply_qt(u, h->stream) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
+  // the tickets belong to the handle's stream (panel kernels use them too)
+  if (st == h->stream) u.tickets = panel_tickets(h);
+  TraceScope ts(h, CAQR_TRACE_UPDATE_T, idx, p.m, k, p.b, p.L, st);
+  return launch_apply_qt(u, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
 }
 
 // Factor every panel in order, updating the trailing matrix after each one
 // (the panel loop of Algorithm 1).  With more than one panel the loop looks
-// ahead: the next panel's columns are updated first, the next panel is
-// factored on a second stream while the rest of the trailing matrix is
-// updated, and the following update waits for it.  Every launch is ordered
-// by stream order or by an event, and all work ends on the handle's stream.
+// ahead: the next panel's columns are updated first, then the next panel is
+// factored on the handle's stream while the rest of the trailing matrix is
+// updated on a second stream; the next panel's own update waits for that.
+// The panel goes right behind the narrow update in its stream, so its few
+// workgroups are dispatched before the wide update fills the device.  Every
+// launch is ordered by stream order or by an event, and all work ends on the
+// handle's stream.
 caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) {
   size_t need = 0;
   for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L);
@@ -345,17 +351,20 @@ caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) 
     const int64_t k = F->n - c0;
     if (k <= 0) break;
     if (!ahead || idx + 1 >= P) {
-      if ((st = launch_trailing(h, F, idx, c0, k))) return st;
+      if ((st = launch_trailing(h, F, idx, c0, k, h->stream))) return st;
       continue;
     }
     const int64_t kn = F->panels[idx + 1].b;  // columns of the next panel
-    if ((st = launch_trailing(h, F, idx, c0, kn))) return st;
-    if (hipEventRecord(h->sync_ev[0], h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
-    if (hipStreamWaitEvent(h->side, h->sync_ev[0], 0) != hipSuccess) return CAQR_ERR_DEVICE;
-    if ((st = launch_panel(h, F, idx + 1, form_t, h->side))) return st;
-    if (hipEventRecord(h->sync_ev[1], h->side) != hipSuccess) return CAQR_ERR_DEVICE;
-    if (k > kn && (st = launch_trailing(h, F, idx, c0 + kn, k - kn))) return st;
-    if (hipStreamWaitEvent(h->stream, h->sync_ev[1], 0) != hipSuccess) return CAQR_ERR_DEVICE;
+    if ((st = launch_trailing(h, F, idx, c0, kn, h->stream))) return st;
+    const bool wide = k > kn;
+    if (wide) {
+      if (hipEventRecord(h->sync_ev[0], h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+      if (hipStreamWaitEvent(h->side, h->sync_ev[0], 0) != hipSuccess) return CAQR_ERR_DEVICE;
+      if ((st = launch_trailing(h, F, idx, c0 + kn, k - kn, h->side))) return st;
+      if (hipEventRecord(h->sync_ev[1], h->side) != hipSuccess) return CAQR_ERR_DEVICE;
+    }
+    if ((st = launch_panel(h, F, idx + 1, form_t, h->stream))) return st;
+    if (wide && hipStreamWaitEvent(h->stream, h->sync_ev[1], 0) != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return CAQR_SUCCESS;
 }

@@ -41,6 +41,8 @@ struct UpdateParams {
   int tiles;          // column tiles of kUpdTile
   int group;          // leaves per workgroup of the Q^T kernel (power of two)
   int level;          // node kernels: tree level processed (half = 1 << (level-1))
+  unsigned *tickets;  // [L] zero on entry and exit, or null; with tickets, a
+                      // single-tile Q^T runs the whole tree in one launch
 };
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s);

@@ -32,7 +32,6 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
-#include "tfactor.hpp"
 
 namespace caqr {
 
@@ -388,89 +387,6 @@ hipError_t launch_panel_nq(const PanelParams &p, hipStream_t s) {
   }
 }
 
-constexpr int kLdG = kMaxB + 1;  // padded leading dimension of G and T in LDS
-
-struct TSmem {
-  double G[kMaxB * kLdG];  // strictly upper Y^T Y
-  double T[kMaxB * kLdG];
-  double taus[kMaxB];
-};
-
-// T of one leaf (blockIdx.x < L) or tree node (blockIdx.x = L + node id) of a
-// factored panel; all leaves and nodes of the panel are independent, so they
-// run in one launch.  G = Y^T Y on FP64 MFMA: each wave accumulates every
-// 16x16 block on or above the diagonal over a quarter of the rows (leaf: Y
-// unit lower trapezoidal, h rows; node: [I; V] with V upper triangular, whose
-// identity part adds nothing off the diagonal), the four partial sums are
-// added in LDS in wave order, then T follows from G and tau.
-template <int NQ>
-__global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
-  __shared__ TSmem sm;
-  const bool is_leaf = (int)blockIdx.x < f.L;
-  const int idx = is_leaf ? (int)blockIdx.x : (int)blockIdx.x - f.L;
-  if (!is_leaf && idx == 0) return;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int64_t row0 = (int64_t)idx * f.h;
-  const int rows = is_leaf ? f.h : 16 * NQ;  // a multiple of 16
-  const int per = rows / 4;                    // rows of each wave, a multiple of 4
-  if (threadIdx.x < kMaxB) {
-    const double *tau = is_leaf ? f.tau_leaf : f.tau_node;
-    sm.taus[threadIdx.x] = (threadIdx.x < f.b) ? tau[(int64_t)idx * kMaxB + threadIdx.x] : 0.0;
-  }
-  f64x4 g[NQ][NQ];
-#pragma unroll
-  for (int a = 0; a < NQ; ++a)
-#pragma unroll
-    for (int c = 0; c < NQ; ++c) g[a][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < per; s += 4) {
-    const int row = wave * per + s + lk;
-    const int64_t grow = row0 + row;
-    double y[NQ];
-#pragma unroll
-    for (int a = 0; a < NQ; ++a) {
-      const int col = 16 * a + li;
-      double e = 0.0;
-      if (col < f.b && grow < f.m) {
-        if (is_leaf)
-          e = (row == col) ? 1.0 : ((row > col) ? f.Y[grow + (int64_t)col * f.ldy] : 0.0);
-        else
-          e = (row <= col) ? f.Y[grow + (int64_t)col * f.ldy] : 0.0;
-      }
-      y[a] = e;
-    }
-#pragma unroll
-    for (int a = 0; a < NQ; ++a)
-#pragma unroll
-      for (int c = a; c < NQ; ++c) g[a][c] = mfma16x16x4(y[a], y[c], g[a][c]);
-  }
-  // G(16a + i, 16c + j), i = 4 r + lk, j = li, in register r of block (a, c)
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int a = 0; a < NQ; ++a)
-#pragma unroll
-        for (int c = a; c < NQ; ++c)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = 16 * a + 4 * r + lk, k = 16 * c + li;
-            if (i < k) sm.G[i * kLdG + k] = (w == 0) ? g[a][c][r] : sm.G[i * kLdG + k] + g[a][c][r];
-          }
-    }
-    __syncthreads();
-  }
-  form_t_lds<NQ>(f.b, sm.G, sm.T, sm.taus, kLdG);
-  store_t_global(is_leaf ? f.T_leaf + (int64_t)idx * kMaxB * kMaxB : f.T_node + (int64_t)idx * kMaxB * kMaxB, f.b,
-                 sm.T, kLdG);
-}
-
-template <int NQ>
-hipError_t launch_form_t_nq(const FormTParams &f, hipStream_t s) {
-  hipLaunchKernelGGL((form_t_kernel<NQ>), dim3(2 * f.L), dim3(kThreads), 0, s, f);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s) {
@@ -479,17 +395,6 @@ hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s)
     case 64: return launch_panel_nq<4>(p, s);
     case 128: return launch_panel_nq<8>(p, s);
     case 256: return launch_panel_nq<16>(p, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_form_t(const FormTParams &f, hipStream_t s) {
-  if (f.b < 1 || f.b > kMaxB || f.L < 1 || f.h % 16 != 0) return hipErrorInvalidValue;
-  switch ((f.b + 15) / 16) {
-    case 1: return launch_form_t_nq<1>(f, s);
-    case 2: return launch_form_t_nq<2>(f, s);
-    case 3: return launch_form_t_nq<3>(f, s);
-    case 4: return launch_form_t_nq<4>(f, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,134 @@
+// Triangular factors T of the compact WY form (Q = I - Y T Y^T) of every leaf
+// and tree node of a factored panel (paper, Section 3.1: the updates of
+// Algorithm 1 apply each leaf's and each node's reflectors as one block).
+//
+// One workgroup per leaf or node, all in one launch.  G = Y^T Y is computed
+// on FP64 MFMA from 64-row chunks of the reflectors staged through LDS
+// (coalesced loads, double-buffered); its 16x16 blocks on and above the
+// diagonal are divided among the four waves, so each block is complete in one
+// wave.  T then follows from G and tau by the blocked recurrence.
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "staging.hpp"
+#include "tfactor.hpp"
+
+namespace caqr {
+
+namespace {
+
+struct TSmem {
+  alignas(16) double buf[2][kMaxB * kLdb];  // reflector chunks; then G (buf 0) and T (buf 1)
+  double taus[kMaxB];
+};
+
+// Block pair number p (0 .. NQ(NQ+1)/2 - 1) -> (a, c), a <= c, row by row.
+template <int NQ>
+__device__ constexpr void block_pair(int p, int &a, int &c) {
+  a = 0;
+  int rem = p;
+  while (rem >= NQ - a) {
+    rem -= NQ - a;
+    ++a;
+  }
+  c = a + rem;
+}
+
+// blockIdx.x < L: leaf blockIdx.x (unit lower-trapezoidal Y of h rows);
+// otherwise node blockIdx.x - L, whose reflectors are [I; V] with V upper
+// triangular (the identity adds nothing off the diagonal of G).
+template <int NQ>
+__global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
+  constexpr int NP = NQ * (NQ + 1) / 2;  // block pairs
+  constexpr int PW = (NP + 3) / 4;       // pairs per wave (at most)
+  __shared__ TSmem sm;
+  const bool is_leaf = (int)blockIdx.x < f.L;
+  const int idx = is_leaf ? (int)blockIdx.x : (int)blockIdx.x - f.L;
+  if (!is_leaf && idx == 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t row0 = (int64_t)idx * f.h;
+  const int nch = is_leaf ? (f.h + 63) / 64 : 1;
+  const bool vec_ok = (((uintptr_t)f.Y & 15) == 0) && (f.ldy % 2 == 0);
+  if (tid < kMaxB) {
+    const double *tau = is_leaf ? f.tau_leaf : f.tau_node;
+    sm.taus[tid] = (tid < f.b) ? tau[(int64_t)idx * kMaxB + tid] : 0.0;
+  }
+  Stage st;
+  if (is_leaf) {
+    stage_load<kLeafY>(st, f.Y, f.ldy, row0, row0, f.m, f.b, vec_ok, tid);
+    stage_fix<kLeafY>(st, 0, tid);
+  } else {
+    stage_load<kNodeV>(st, f.Y, f.ldy, row0, row0, f.m, f.b, vec_ok, tid);
+    stage_fix<kNodeV>(st, 0, tid);
+  }
+  stage_store(st, sm.buf[0], tid);
+  __syncthreads();
+  f64x4 g[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) g[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) stage_load<kLeafY>(st, f.Y, f.ldy, row0 + 64 * (c + 1), row0, f.m, f.b, vec_ok, tid);
+    const double *ys = sm.buf[c & 1];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int p = wave + 4 * q;
+      if (p >= NP) continue;
+      int a, cc;
+      block_pair<NQ>(p, a, cc);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        // slabs that hold only zeros of both blocks are skipped
+        if (c == 0 && (is_leaf ? tt < cc : tt > a)) continue;
+        const f64x4 ya = lds_col4(ys, 16 * a + li, 16 * tt + 4 * lk);
+        const f64x4 yc = lds_col4(ys, 16 * cc + li, 16 * tt + 4 * lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[q] = mfma16x16x4(ya[r], yc[r], g[q]);
+      }
+    }
+    if (c + 1 < nch) stage_store(st, sm.buf[(c + 1) & 1], tid);
+    __syncthreads();
+  }
+  // strictly upper G into buffer 0: register r of lane (li, lk) of pair (a, c)
+  // holds G(16a + 4r + lk, 16c + li)
+  double *G = sm.buf[0];
+  double *T = sm.buf[1];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    const int p = wave + 4 * q;
+    if (p >= NP) continue;
+    int a, cc;
+    block_pair<NQ>(p, a, cc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * a + 4 * r + lk, k = 16 * cc + li;
+      if (i < k) G[i * kLdb + k] = g[q][r];
+    }
+  }
+  __syncthreads();
+  form_t_lds<NQ>(f.b, G, T, sm.taus, kLdb);
+  store_t_global(is_leaf ? f.T_leaf + (int64_t)idx * kMaxB * kMaxB : f.T_node + (int64_t)idx * kMaxB * kMaxB, f.b, T,
+                 kLdb);
+}
+
+template <int NQ>
+hipError_t launch_form_t_nq(const FormTParams &f, hipStream_t s) {
+  hipLaunchKernelGGL((form_t_kernel<NQ>), dim3(2 * f.L), dim3(kThreads), 0, s, f);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_form_t(const FormTParams &f, hipStream_t s) {
+  if (f.b < 1 || f.b > kMaxB || f.L < 1 || f.h < 1) return hipErrorInvalidValue;
+  switch ((f.b + 15) / 16) {
+    case 1: return launch_form_t_nq<1>(f, s);
+    case 2: return launch_form_t_nq<2>(f, s);
+    case 3: return launch_form_t_nq<3>(f, s);
+    case 4: return launch_form_t_nq<4>(f, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace caqr

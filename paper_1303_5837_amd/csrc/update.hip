@@ -28,14 +28,11 @@
 // row pi(lane%16) = 4*(lane%4) + (lane%16)/4 of the slab.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "staging.hpp"
 
 namespace caqr {
 
 namespace {
-
-constexpr int kLdb = 68;   // leading dimension (doubles) of a staged 64x64 block in LDS
-
-typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 struct UpdSmem {
   alignas(16) double buf[2][kMaxB * kLdb];
@@ -45,89 +42,6 @@ struct UpdSmem {
 __device__ __forceinline__ int pi16(int li) { return 4 * (li & 3) + (li >> 2); }
 
 __device__ __forceinline__ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
-
-enum BlockKind { kLeafY = 0, kNodeV = 1, kDense = 2 };
-
-// A 64x64 block staged through registers: thread tid holds 8 row pairs.
-// Pair e = s*256 + tid (s = 0..7): column e / 32, block rows 2*(e % 32) and +1.
-struct Stage {
-  f64x2 v[8];
-};
-
-// Load a 64x64 block of reflectors (or T) from global memory into registers:
-// block rows 0..63 are the panel rows src0..src0+63.  For KIND kLeafY, `lr_off`
-// converts a panel row to the row within the leaf (lr = row - lr_off) and the
-// value is the unit lower-trapezoidal leaf reflector; kNodeV: the upper
-// triangular V whose row 0 is panel row lr_off; kDense: a dense 64x64
-// column-major block, ld 64 (T).
-template <int KIND>
-__device__ __forceinline__ void stage_load(Stage &st, const double *base, int64_t ld, int64_t src0, int64_t lr_off,
-                                           int64_t m, int b, bool vec_ok, int tid) {
-  const int row = 2 * (tid & 31);  // block row pair of this thread (same for every s)
-  const int colt = tid >> 5;       // block column for s = 0; s adds 8
-  if (KIND == kDense) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) st.v[s] = *reinterpret_cast<const f64x2 *>(base + row + 64 * (colt + 8 * s));
-    return;
-  }
-  const int64_t g0 = src0 + row;
-  const int64_t lr = g0 - lr_off;
-  // uniform fast path: full-width panel, every row in range, 16-byte aligned
-  const bool fast = vec_ok && b == kMaxB && src0 + 63 < m;
-  if (fast) {
-    const double *p = base + g0 + (int64_t)colt * ld;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int col = colt + 8 * s;
-      const f64x2 t = *reinterpret_cast<const f64x2 *>(p + (int64_t)(8 * s) * ld);
-      double x0 = t.x, x1 = t.y;
-      if (KIND == kLeafY) {
-        x0 = (lr > col) ? x0 : ((lr == col) ? 1.0 : 0.0);
-        x1 = (lr + 1 > col) ? x1 : ((lr + 1 == col) ? 1.0 : 0.0);
-      } else {
-        x0 = (lr <= col) ? x0 : 0.0;
-        x1 = (lr + 1 <= col) ? x1 : 0.0;
-      }
-      st.v[s] = f64x2{x0, x1};
-    }
-    return;
-  }
-  const int64_t ga = min(g0, m - 1), gb = min(g0 + 1, m - 1);
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int col = colt + 8 * s;
-    const int64_t cc = (int64_t)min(col, b - 1) * ld;
-    double x0 = base[ga + cc], x1 = base[gb + cc];
-    const bool okc = col < b;
-    if (KIND == kLeafY) {
-      x0 = (okc && g0 < m && lr > col) ? x0 : ((okc && lr == col) ? 1.0 : 0.0);
-      x1 = (okc && g0 + 1 < m && lr + 1 > col) ? x1 : ((okc && lr + 1 == col) ? 1.0 : 0.0);
-    } else {  // node V: upper triangle including the diagonal
-      x0 = (okc && g0 < m && lr <= col) ? x0 : 0.0;
-      x1 = (okc && g0 + 1 < m && lr + 1 <= col) ? x1 : 0.0;
-    }
-    st.v[s] = f64x2{x0, x1};
-  }
-}
-
-__device__ __forceinline__ void stage_store(const Stage &st, double *lds, int tid) {
-  double *p = lds + (tid >> 5) * kLdb + 2 * (tid & 31);
-#pragma unroll
-  for (int s = 0; s < 8; ++s) *reinterpret_cast<f64x2 *>(p + 8 * s * kLdb) = st.v[s];
-}
-
-// Four consecutive rows row0..row0+3 of column col of a staged block.
-__device__ __forceinline__ f64x4 lds_col4(const double *lds, int col, int row0) {
-  const f64x2 lo = *reinterpret_cast<const f64x2 *>(lds + col * kLdb + row0);
-  const f64x2 hi = *reinterpret_cast<const f64x2 *>(lds + col * kLdb + row0 + 2);
-  return f64x4{lo.x, lo.y, hi.x, hi.y};
-}
-
-// Four consecutive columns col0..col0+3 of row `row` of a staged block.
-__device__ __forceinline__ f64x4 lds_row4(const double *lds, int row, int col0) {
-  return f64x4{lds[col0 * kLdb + row], lds[(col0 + 1) * kLdb + row], lds[(col0 + 2) * kLdb + row],
-               lds[(col0 + 3) * kLdb + row]};
-}
 
 // C slab load/store (contiguous layout) with row/column masking.
 __device__ __forceinline__ f64x4 load_slab(const double *C, int64_t ldc, int64_t grow, int64_t col, int64_t m,
@@ -199,6 +113,7 @@ __device__ __forceinline__ void node_update(const UpdateParams &u, int left, int
   const int64_t m1 = min<int64_t>(u.m, r1 + u.b), m2 = min<int64_t>(u.m, r2 + u.b);
   Stage st;
   stage_load<kNodeV>(st, u.Y, u.ldy, r2, r2, u.m, u.b, vec_ok, tid);
+  stage_fix<kNodeV>(st, 0, tid);
   stage_store(st, sm.buf[0], tid);
   stage_load<kDense>(st, u.T_node + (int64_t)node * 64 * 64, 64, 0, 0, 0, 0, true, tid);
   stage_store(st, sm.buf[1], tid);
@@ -272,15 +187,39 @@ __device__ __forceinline__ void scale_top_rows_own(const UpdateParams &u, int ti
     }
 }
 
+// Whether the whole leaf x tile block of C is in range and 16-byte aligned
+// (uniform fast path for C).
+__device__ __forceinline__ bool leaf_cfast(const UpdateParams &u, int leaf, int tile) {
+  return aligned16(u.C) && (u.ldc % 2 == 0) && (int64_t)(leaf + 1) * u.h <= u.m &&
+         (int64_t)(tile + 1) * kUpdTile <= u.k;
+}
+
+__device__ __forceinline__ f64x4 ld_c4(const double *p) {
+  const f64x2 lo = *reinterpret_cast<const f64x2 *>(p);
+  const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 2);
+  return f64x4{lo.x, lo.y, hi.x, hi.y};
+}
+
+__device__ __forceinline__ void st_c4(double *p, f64x4 v) {
+  *reinterpret_cast<f64x2 *>(p) = f64x2{v[0], v[1]};
+  *reinterpret_cast<f64x2 *>(p + 2) = f64x2{v[2], v[3]};
+}
+
 // Q^T (TRANS) or Q update of one leaf on one tile: C_leaf <- C_leaf - Y (T^T (Y^T C_leaf)).
 // Wave w holds all H rows of the leaf for columns 16w..16w+15 in registers
 // (RT slabs of 16 rows), so both products are complete inside the wave.  The
 // reflectors go through LDS in 64-row chunks, double-buffered: chunks 0..n-1
 // for W = Y^T C, then T, then chunks n-1..0 for C -= Y W' (the last chunk of
 // the first pass is still in LDS and is not reloaded).  Chunk c always sits in
-// buffer c % 2; T sits in buffer n % 2.
+// buffer c % 2; T sits in buffer n % 2.  Inside a chunk the LDS operands of
+// the next 16-row slab are read before the products of the current one.
+// Every chunk of C is stored as soon as it is final.  `pre` carries the first
+// 64 rows of this leaf's tile when the previous call prefetched them
+// (has_pre); with next >= 0 this call prefetches those rows of leaf `next`
+// during its second pass.
 template <int NQ, int RT, bool TRANS>
-__device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int tile, UpdSmem &sm) {
+__device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int tile, UpdSmem &sm, f64x4 (&pre)[4],
+                                            bool has_pre, int next) {
   constexpr int H = 16 * RT;       // leaf rows
   constexpr int NCHUNK = H / 64;   // 64-row chunks
   const int tid = threadIdx.x;
@@ -296,21 +235,22 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
 
   Stage st;
   stage_load<kLeafY>(st, u.Y, u.ldy, row0, row0, u.m, u.b, vec_y, tid);
-  // uniform fast path for C: the whole leaf x tile block in range and aligned
-  const bool cfast = vec_c && row0 + H <= u.m && (int64_t)(tile + 1) * kUpdTile <= u.k;
+  const bool cfast = leaf_cfast(u, leaf, tile);
   double *cptr = u.C + row0 + 4 * lk + col * u.ldc;
   f64x4 acc[RT];  // rows row0 + 16x + 4lk + r
   if (cfast) {
 #pragma unroll
     for (int x = 0; x < RT; ++x) {
-      const f64x2 lo = *reinterpret_cast<const f64x2 *>(cptr + 16 * x);
-      const f64x2 hi = *reinterpret_cast<const f64x2 *>(cptr + 16 * x + 2);
-      acc[x] = f64x4{lo.x, lo.y, hi.x, hi.y};
+      if (x < 4 && has_pre)
+        acc[x] = pre[x];
+      else
+        acc[x] = ld_c4(cptr + 16 * x);
     }
   } else {
 #pragma unroll
     for (int x = 0; x < RT; ++x) acc[x] = load_slab(u.C, u.ldc, row0 + 16 * x + 4 * lk, col, u.m, colok, vec_c);
   }
+  stage_fix<kLeafY>(st, 0, tid);
   stage_store(st, sm.buf[0], tid);
   __syncthreads();
 
@@ -325,57 +265,85 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
     else
       stage_load<kDense>(st, u.T_leaf + (int64_t)leaf * 64 * 64, 64, 0, 0, 0, 0, true, tid);
     const double *ys = sm.buf[c & 1];
+    f64x4 y[2][NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+      if (4 * c >= a) y[0][a] = lds_col4(ys, 16 * a + pl, 4 * lk);
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
       const int x = 4 * c + tt;  // slab index within the leaf
+      if (tt + 1 < 4) {
 #pragma unroll
-      for (int a = 0; a < NQ; ++a) {
-        if (x < a) continue;  // slab rows lie above the reflectors of block a
-        const f64x4 y = lds_col4(ys, 16 * a + pl, 16 * tt + 4 * lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(y[r], acc[x][r], w[a]);
+        for (int a = 0; a < NQ; ++a)
+          if (x + 1 >= a) y[(tt + 1) & 1][a] = lds_col4(ys, 16 * a + pl, 16 * (tt + 1) + 4 * lk);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 0; a < NQ; ++a)
+          if (x >= a) w[a] = mfma16x16x4(y[tt & 1][a][r], acc[x][r], w[a]);  // rows above block a are zero
     }
     stage_store(st, sm.buf[(c + 1) & 1], tid);
     __syncthreads();
   }
-  // ---- W' = T^T W (T in buffer NCHUNK % 2); the next chunk of the second
+  // ---- W' = -T^T W (T in buffer NCHUNK % 2); the next chunk of the second
   // pass (NCHUNK - 2) is loaded meanwhile and goes into T's buffer afterwards
   if (NCHUNK > 1) stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (NCHUNK - 2), row0, u.m, u.b, vec_y, tid);
   apply_t_lds<NQ, TRANS>(sm.buf[NCHUNK & 1], w);
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) w[a] = -w[a];
+  if (next >= 0) {  // first 64 rows of the next leaf's tile (fast path; the caller checked)
+    const double *np = u.C + (int64_t)next * u.h + 4 * lk + col * u.ldc;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) pre[x] = ld_c4(np + 16 * x);
+  }
   __syncthreads();
-  // ---- C -= Y W', chunks NCHUNK-1 .. 0
+  // ---- C += Y W', chunks NCHUNK-1 .. 0
 #pragma unroll
   for (int c = NCHUNK - 1; c >= 0; --c) {
     if (c >= 1) {
+      if (c == 1) stage_fix<kLeafY>(st, 0, tid);   // chunk 0 holds the diagonal
       stage_store(st, sm.buf[(c - 1) & 1], tid);  // chunk c - 1 into the buffer chunk c + 1 (or T) left
       if (c >= 2) stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (c - 2), row0, u.m, u.b, vec_y, tid);
     }
     const double *ys = sm.buf[c & 1];
+    f64x4 y[2][NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+      if (4 * c >= a) y[0][a] = lds_row4(ys, pl, 16 * a + 4 * lk);
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
       const int x = 4 * c + tt;
+      if (tt + 1 < 4) {
 #pragma unroll
-      for (int a = 0; a < NQ; ++a) {
-        if (x < a) continue;
-        const f64x4 y = lds_row4(ys, 16 * tt + pl, 16 * a + 4 * lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(-y[r], w[a][r], acc[x]);
+        for (int a = 0; a < NQ; ++a)
+          if (x + 1 >= a) y[(tt + 1) & 1][a] = lds_row4(ys, 16 * (tt + 1) + pl, 16 * a + 4 * lk);
       }
+#pragma unroll
+      for (int a = 0; a < NQ; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (x >= a) acc[x] = mfma16x16x4(y[tt & 1][a][r], w[a][r], acc[x]);
+    }
+    // rows of chunk c are final
+    if (cfast) {
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) st_c4(cptr + 16 * (4 * c + tt), acc[4 * c + tt]);
+    } else {
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+        store_slab(u.C, u.ldc, row0 + 16 * (4 * c + tt) + 4 * lk, col, u.m, colok, vec_c, acc[4 * c + tt]);
     }
     if (c >= 1) __syncthreads();
   }
-  if (cfast) {
-#pragma unroll
-    for (int x = 0; x < RT; ++x) {
-      *reinterpret_cast<f64x2 *>(cptr + 16 * x) = f64x2{acc[x][0], acc[x][1]};
-      *reinterpret_cast<f64x2 *>(cptr + 16 * x + 2) = f64x2{acc[x][2], acc[x][3]};
-    }
-  } else {
-#pragma unroll
-    for (int x = 0; x < RT; ++x) store_slab(u.C, u.ldc, row0 + 16 * x + 4 * lk, col, u.m, colok, vec_c, acc[x]);
-  }
   __syncthreads();  // LDS free for the next update
+}
+
+// One leaf update with no prefetch on either side.
+template <int NQ, int RT, bool TRANS>
+__device__ __forceinline__ void leaf_update_single(const UpdateParams &u, int leaf, int tile, UpdSmem &sm) {
+  f64x4 pre[4];
+  leaf_update<NQ, RT, TRANS>(u, leaf, tile, sm, pre, false, -1);
 }
 
 // Q^T of one panel on one tile, for the leaves of group g (u.group leaves,
@@ -392,8 +360,15 @@ __global__ void __launch_bounds__(kThreads, 1) qt_group_kernel(UpdateParams u) {
   const int tile = blockIdx.x / ngroups;
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
   const int first = g * u.group, last = min(u.L, first + u.group);
+  f64x4 pre[4];
+  bool has_pre = false;
 #pragma nounroll
-  for (int leaf = first; leaf < last; ++leaf) leaf_update<NQ, RT, true>(u, __builtin_amdgcn_readfirstlane(leaf), tile, sm);
+  for (int leaf = first; leaf < last; ++leaf) {
+    const int lf = __builtin_amdgcn_readfirstlane(leaf);
+    const int next = (lf + 1 < last && leaf_cfast(u, lf + 1, tile)) ? lf + 1 : -1;
+    leaf_update<NQ, RT, true>(u, lf, tile, sm, pre, has_pre, next);
+    has_pre = next >= 0;
+  }
   for (int half = 1; half < u.group && half < u.L; half <<= 1)
 #pragma nounroll
     for (int node = first + half; node < last; node += 2 * half)
@@ -407,7 +382,7 @@ __global__ void __launch_bounds__(kThreads, 1) qn_leaf_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
   const int leaf = blockIdx.x % u.L;
   const int tile = blockIdx.x / u.L;
-  leaf_update<NQ, RT, false>(u, leaf, tile, sm);
+  leaf_update_single<NQ, RT, false>(u, leaf, tile, sm);
 }
 
 template <int NQ, bool TRANS>
@@ -426,8 +401,59 @@ __global__ void __launch_bounds__(kThreads, 2) node_level_kernel(UpdateParams u)
 
 __global__ void scale_rows_kernel(UpdateParams u) { scale_top_rows(u, blockIdx.x); }
 
+// Last-arriver ticket on node `node`; true when this workgroup arrived second
+// (and performs the node's update).  Publishes this workgroup's stores to C
+// before the ticket and acquires the partner's after it.
+__device__ __forceinline__ bool arrive(unsigned *tickets, int node, int &flag) {
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned old = ticket_add(tickets + node);
+    flag = (int)old;
+    if (old == 1u) ticket_clear(tickets + node);
+  }
+  __syncthreads();
+  const bool second = flag == 1;
+  if (second) fence_acquire();
+  return second;
+}
+
+// Q^T of one panel on a single tile (at most 64 columns, e.g. the next
+// panel's), the whole tree in one launch: workgroup i updates leaf i, then
+// climbs the binary tree; below every node the second workgroup to arrive (an
+// agent-scope ticket) performs the node's update, the first one exits.  The
+// pairing is fixed by index, so the result does not depend on arrival order.
+// The workgroup that completes the root applies D.
+template <int NQ, int RT>
+__global__ void __launch_bounds__(kThreads, 1) qt_tree_tile_kernel(UpdateParams u) {
+  __shared__ UpdSmem sm;
+  __shared__ int flag;
+  const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
+  const int leaf = blockIdx.x;
+  leaf_update_single<NQ, RT, true>(u, leaf, 0, sm);
+  int rt = leaf;  // root of the subtree this workgroup holds
+  for (int half = 1; half < u.L; half <<= 1) {
+    if ((rt & (2 * half - 1)) == 0) {  // left child at this level
+      const int partner = rt + half;
+      if (partner >= u.L) continue;      // no sibling: pass through
+      if (!arrive(u.tickets, partner, flag)) return;
+      node_update<NQ, true>(u, rt, partner, 0, sm, vec_ok);
+    } else {  // right child: node id rt, left sibling rt - half
+      const int left = rt - half;
+      if (!arrive(u.tickets, rt, flag)) return;
+      node_update<NQ, true>(u, left, rt, 0, sm, vec_ok);
+      rt = left;
+    }
+  }
+  scale_top_rows_own<NQ>(u, 0);
+}
+
 template <int NQ, int RT>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
+  if (u.tickets && u.tiles == 1 && u.L > 1) {
+    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT>), dim3(u.L), dim3(kThreads), 0, s, u);
+    return hipGetLastError();
+  }
   const int ngroups = (u.L + u.group - 1) / u.group;
   hipLaunchKernelGGL((qt_group_kernel<NQ, RT>), dim3(ngroups * u.tiles), dim3(kThreads), 0, s, u);
   if (ngroups > 1) {
