@@ -37,6 +37,32 @@ def update_flops(rows: int, cols: int, b: int, leaves: int) -> float:
     return cols * (4.0 * rows * b + leaves * b * b + 3.0 * (leaves - 1) * b * b)
 
 
+UPDATE_SOURCES = ("update.hip", "staging.hpp", "kernels.hpp", "device_common.hpp")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "caqr_8192_update_traffic.md")
+
+
+def update_traffic_per_call():
+    """Measured HBM bytes per trailing-update call (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, scaled by the same counters on a plain copy), from the committed
+    profile summary; None when the update's sources changed since it was taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m_b = re.search(r"update_traffic_bytes_per_call: (\d+)", text)
+    m_h = re.search(r"update_sources_sha256: ([0-9a-f]+)", text)
+    if not (m_b and m_h):
+        return None
+    h = hashlib.sha256()
+    for f in UPDATE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1303_5837_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_b.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
 def panel_bytes(rows: int, b: int) -> float:
     """Algorithmic HBM bytes of one panel factorization: read A, write Y/R."""
     return 16.0 * rows * b
@@ -105,6 +131,7 @@ def main():
 
     upd = [e for e in trace if e["kind"] == "update_t"]
     pan = [e for e in trace if e["kind"] == "panel"]
+    upd_alg_bytes = sum(16.0 * e["rows"] * e["cols"] for e in upd) / max(1, len(upd))
     upd_ms = sum(e["ms"] for e in upd)
     upd_flops = sum(update_flops(e["rows"], e["cols"], e["width"], e["leaves"]) for e in upd)
     achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
@@ -130,13 +157,16 @@ def main():
         "step_ms": [round(x, 4) for x in step_ms],
         "wall_ms_timed_region": round(wall_ms, 2),
         "roofline": {
-            "kernel": "leaf_update_kernel (trailing update, Q^T, fused tree levels)",
+            "kernel": "trailing update call Q_s^T C (qt_group_kernel + per-level node_level_kernel + "
+                      "scale_rows_kernel; qt_tree_tile_kernel for the next panel's columns)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-            "traffic": None,
+            "traffic": update_traffic_per_call(),
+            "traffic_unit": "HBM bytes per update call (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "traffic_algorithmic": round(upd_alg_bytes),
             "launches_per_step": len(upd) // max(1, args.steps),
             "avg_launch_ms": round(upd_ms / max(1, len(upd)), 5),
             "update_share_of_step": round(upd_ms / max(1e-9, sum(step_ms)), 4),
@@ -177,7 +207,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        ns = 4096
+        ns = n  # the headline workload itself: about 15-30 s of CPU work on 16 cores
         S = inputs.gaussian(ns, ns, inputs.SEEDS["caqr_8192sq"])
         t0 = time.perf_counter()
         oracle.qr_r(S)
