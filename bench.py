@@ -202,6 +202,46 @@ def main():
                         "gflops": round((2.0 * m2 * n2 * n2 - 2.0 * n2 ** 3 / 3) / (t * 1e-3) / 1e9, 1),
                         "algorithmic_GBps": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / PEAK_HBM_GBS, 2)}
             del B0, B
+        # uneven batch (2000 problems, m log-uniform in [256, 65536], n in {8,16,32,64}),
+        # plans from the autotuner; one step = one tsqr_factor_batched call
+        ms, ns = inputs.batched_tsqr_sizes()
+        seed = inputs.SEEDS["batched_tsqr"]
+        P = [inputs.gaussian_device(int(m), int(n), seed * 100003 + i) for i, (m, n) in enumerate(zip(ms, ns))]
+        W = [torch.empty_like(a.t()).t() for a in P]
+        t_tune = time.perf_counter()
+        caqr.tune_batched()
+        t_tune = time.perf_counter() - t_tune
+        times = []
+        for it in range(3 + 10):
+            for w, a in zip(W, P):
+                w.copy_(a)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            Bt = caqr.tsqr_batched(W)
+            e1.record()
+            torch.cuda.synchronize()
+            if it >= 3:
+                times.append(e0.elapsed_time(e1))
+            Bt.close()
+        t = float(np.median(times))
+        alg = float(sum(16.0 * int(m) * int(n) for m, n in zip(ms, ns)))
+        flops = float(sum(2.0 * int(m) * int(n) ** 2 - 2.0 * int(n) ** 3 / 3 for m, n in zip(ms, ns)))
+        plans = {}
+        for m, n in zip(ms, ns):
+            k = "h%d/lpw%d" % caqr.batch_plan_for(int(m), int(n))
+            plans[k] = plans.get(k, 0) + 1
+        sec["batched_tsqr_2000_uneven"] = {
+            "median_ms": round(t, 4), "p10_ms": round(float(np.percentile(times, 10)), 4),
+            "p90_ms": round(float(np.percentile(times, 90)), 4),
+            "matrices_per_s": round(len(ms) / (t * 1e-3), 1), "gflops": round(flops / (t * 1e-3) / 1e9, 1),
+            "algorithmic_GBps": round(alg / (t * 1e-3) / 1e9, 1),
+            "pct_hbm_peak": round(100 * alg / (t * 1e-3) / 1e9 / PEAK_HBM_GBS, 2),
+            "bytes": alg, "tune_s": round(t_tune, 2), "plans": plans,
+            "timed": "one tsqr_factor_batched call incl. planning and table upload (HIP events)"}
+        del P, W
+        torch.cuda.empty_cache()
         out["secondary"] = sec
 
     if not args.no_cpu_baseline:

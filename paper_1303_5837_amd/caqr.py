@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcaqr.so")
 
 OP_N, OP_T = 0, 1
+F64, F32 = 0, 1
 
 _STATUS = {
     0: "CAQR_SUCCESS",
@@ -73,6 +74,8 @@ EXPORTS = [
     "caqr_create", "caqr_destroy", "caqr_set_stream", "caqr_get_stream", "caqr_set_workspace_limit", "caqr_sync",
     "caqr_status_string", "caqr_device_count", "tsqr_factor", "caqr_factor", "apply_q", "caqr_factors_destroy",
     "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_trace_read",
+    "tsqr_factor_batched", "caqr_batch_destroy", "caqr_batch_get_plan", "caqr_batch_get_signs", "caqr_tune_batched",
+    "caqr_batch_plan_for",
 ]
 
 
@@ -103,6 +106,14 @@ def _lib():
         L.ls_solve.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(LsOpts), ctypes.POINTER(LsInfo)]
         L.caqr_set_trace.argtypes = [vp, i32]
         L.caqr_trace_read.argtypes = [vp, ctypes.POINTER(TraceEntry), i64, ctypes.POINTER(i64)]
+        pi64 = ctypes.POINTER(i64)
+        L.tsqr_factor_batched.argtypes = [vp, i64, pi64, pi64, ctypes.POINTER(vp), pi64, i32,
+                                          ctypes.POINTER(TreeOpts), ctypes.POINTER(vp)]
+        L.caqr_batch_destroy.argtypes = [vp]
+        L.caqr_batch_get_plan.argtypes = [vp, i64, ctypes.POINTER(TreeOpts)]
+        L.caqr_batch_get_signs.argtypes = [vp, i64, dp]
+        L.caqr_tune_batched.argtypes = [vp, i32]
+        L.caqr_batch_plan_for.argtypes = [vp, i64, i64, i32, ctypes.POINTER(TreeOpts)]
         for name in EXPORTS:
             if name not in ("caqr_status_string",):
                 getattr(L, name).restype = ctypes.c_int
@@ -290,3 +301,67 @@ def ls_solve(A: torch.Tensor, B: torch.Tensor, device: int = 0):
     if code not in (0, 5, 6):
         _check(code, "ls_solve")
     return B[:n], info
+
+
+class Batch:
+    """Owner of a ``caqr_batch_t``; keeps the factored tensors alive."""
+
+    def __init__(self, h: Handle, ptr: ctypes.c_void_p, As):
+        self.h, self._b, self.As = h, ptr, list(As)
+
+    def plan(self, i: int):
+        o = TreeOpts()
+        _check(_lib().caqr_batch_get_plan(self._b, i, ctypes.byref(o)), "caqr_batch_get_plan")
+        return int(o.leaf_rows), int(o.leaves_per_wg)
+
+    def signs(self, i: int):
+        import numpy as np
+
+        d = np.zeros(self.As[i].shape[1])
+        _check(_lib().caqr_batch_get_signs(self._b, i, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "caqr_batch_get_signs")
+        return d
+
+    def R(self, i: int) -> torch.Tensor:
+        n = self.As[i].shape[1]
+        return torch.triu(self.As[i][:n, :n])
+
+    def close(self):
+        if self._b:
+            _lib().caqr_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tsqr_batched(As, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0) -> Batch:
+    """In place TSQR of every column-major CUDA tensor in ``As`` (one plan for all
+    when leaf_rows/leaves_per_wg are given, else the tuned or default plans)."""
+    h = handle(device)
+    k = len(As)
+    m = (ctypes.c_int64 * max(1, k))(*[int(a.shape[0]) for a in As])
+    n = (ctypes.c_int64 * max(1, k))(*[int(a.shape[1]) for a in As])
+    ld = (ctypes.c_int64 * max(1, k))(*[_ld(a) for a in As])
+    ptrs = (ctypes.c_void_p * max(1, k))(*[a.data_ptr() for a in As])
+    b = ctypes.c_void_p()
+    _check(_lib().tsqr_factor_batched(h.ptr, k, m, n, ptrs, ld, F64, _opts(leaf_rows, leaves_per_wg),
+                                      ctypes.byref(b)), "tsqr_factor_batched")
+    return Batch(h, b, As)
+
+
+def tune_batched(device: int = 0):
+    """Measure the batched plans per size bucket (stored in the handle)."""
+    h = handle(device)
+    _check(_lib().caqr_tune_batched(h.ptr, F64), "caqr_tune_batched")
+
+
+def batch_plan_for(m: int, n: int, device: int = 0):
+    """(leaf_rows, leaves_per_wg) a batched call without a plan uses for an m-by-n problem."""
+    h = handle(device)
+    o = TreeOpts()
+    _check(_lib().caqr_batch_plan_for(h.ptr, m, n, F64, ctypes.byref(o)), "caqr_batch_plan_for")
+    return int(o.leaf_rows), int(o.leaves_per_wg)

@@ -47,6 +47,12 @@ struct UpdateParams {
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s);
 
+// Independent panels of equal ceil(b/16) = nq and leaf height in one launch:
+// probs (device) holds one PanelParams per problem, items (device) one
+// (problem, first leaf) pair per workgroup.
+hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items, int nitems, int leaf_rows, int nq,
+                                     hipStream_t s);
+
 // C <- Q^T C for one panel: leaf updates and the tree bottom-up, then rows
 // 0..b-1 scaled by D.  One workgroup per (group of u.group leaves, tile) runs
 // the leaves and the tree levels inside its group; a second launch runs the

@@ -265,16 +265,17 @@ __device__ __forceinline__ bool arrive(const PanelParams &p, int node, PanelSmem
   return second;
 }
 
+// The leaves leaf0 .. leaf0 + lpw - 1 of panel p and the part of its tree
+// this workgroup ends up holding (levels 1-3).
 template <int RPT, int NQ>
-__global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) {
+__device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
+  __shared__ PanelSmem sm;
   constexpr int NCH = (RPT > 2 * NQ) ? RPT : 2 * NQ;
   constexpr int H = 16 * RPT;
-  __shared__ PanelSmem sm;
   double a[NCH][NQ];
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
   const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
-  const int leaf0 = blockIdx.x * p.lpw;
   const int nleaves = min(p.lpw, p.L - leaf0);
 
   for (int li = 0; li < nleaves; ++li) {
@@ -370,6 +371,20 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) 
 
 
 template <int RPT, int NQ>
+__global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) {
+  panel_body<RPT, NQ>(p, blockIdx.x * p.lpw);
+}
+
+// Many independent panels in one launch: workgroup i takes problem
+// items[i].x, leaves from items[i].y on (each problem with its own tickets).
+template <int RPT, int NQ>
+__global__ void __launch_bounds__(kThreads, 2) tsqr_panel_batched_kernel(const PanelParams *probs, const int2 *items) {
+  const int2 it = items[blockIdx.x];
+  const PanelParams p = probs[__builtin_amdgcn_readfirstlane(it.x)];
+  panel_body<RPT, NQ>(p, __builtin_amdgcn_readfirstlane(it.y));
+}
+
+template <int RPT, int NQ>
 hipError_t launch_panel_t(const PanelParams &p, hipStream_t s) {
   const int grid = (p.L + p.lpw - 1) / p.lpw;
   hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ>), dim3(grid), dim3(kThreads), 0, s, p);
@@ -387,7 +402,35 @@ hipError_t launch_panel_nq(const PanelParams &p, hipStream_t s) {
   }
 }
 
+template <int RPT, int NQ>
+hipError_t launch_batched_t(const PanelParams *probs, const int2 *items, int nitems, hipStream_t s) {
+  hipLaunchKernelGGL((tsqr_panel_batched_kernel<RPT, NQ>), dim3(nitems), dim3(kThreads), 0, s, probs, items);
+  return hipGetLastError();
+}
+
+template <int RPT>
+hipError_t launch_batched_nq(int nq, const PanelParams *probs, const int2 *items, int nitems, hipStream_t s) {
+  switch (nq) {
+    case 1: return launch_batched_t<RPT, 1>(probs, items, nitems, s);
+    case 2: return launch_batched_t<RPT, 2>(probs, items, nitems, s);
+    case 3: return launch_batched_t<RPT, 3>(probs, items, nitems, s);
+    case 4: return launch_batched_t<RPT, 4>(probs, items, nitems, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items, int nitems, int leaf_rows, int nq,
+                                     hipStream_t s) {
+  if (nitems < 1 || nq < 1 || nq > 4) return hipErrorInvalidValue;
+  switch (leaf_rows) {
+    case 64: return launch_batched_nq<4>(nq, probs, items, nitems, s);
+    case 128: return launch_batched_nq<8>(nq, probs, items, nitems, s);
+    case 256: return launch_batched_nq<16>(nq, probs, items, nitems, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s) {
   if (p.b < 1 || p.b > kMaxB || p.L < 1 || p.lpw < 1) return hipErrorInvalidValue;

@@ -52,3 +52,13 @@ def geometric_singular_values(n: int, kappa: float) -> np.ndarray:
     if n == 1:
         return np.ones(1)
     return kappa ** (-np.arange(n) / (n - 1.0))
+
+
+def gaussian_device(m: int, n: int, seed: int, device="cuda"):
+    """N(0,1) m-by-n matrix drawn on the GPU (torch's seeded generator), column
+    major: for inputs too large to draw on the host (the full uneven batch)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn((n, m), generator=g, dtype=torch.float64, device=device).t()

@@ -88,3 +88,37 @@ def test_argument_validation_without_device():
     assert lib.caqr_sync(None) == 1
     assert lib.caqr_destroy(None) == 1
     assert lib.caqr_factors_destroy(None) == 1
+
+
+def test_batched_argument_validation_without_device():
+    """tsqr_factor_batched checks every problem before the handle."""
+    lib = caqr.library()
+    A = ctypes.c_void_p(0x1000)
+
+    def call(m, n, ld, ptrs=None, dt=caqr.F64, opts=None, batch=None, F=True):
+        k = len(m) if batch is None else batch
+        M = (ctypes.c_int64 * max(1, len(m)))(*m)
+        N = (ctypes.c_int64 * max(1, len(n)))(*n)
+        LD = (ctypes.c_int64 * max(1, len(ld)))(*ld)
+        P = (ctypes.c_void_p * max(1, len(m)))(*(ptrs if ptrs is not None else [A.value] * len(m)))
+        f = ctypes.c_void_p()
+        return lib.tsqr_factor_batched(None, k, M, N, P, LD, dt, opts, ctypes.byref(f) if F else None)
+
+    assert call([10, 20], [2, 3], [10, 20], batch=-1) == 1          # negative batch
+    assert call([10], [2], [10], F=False) == 1                        # no output pointer
+    assert call([10, 20], [2, 3], [9, 20]) == 1                       # lda < m
+    assert call([10, 20], [2, 3], [10, 20], ptrs=[A.value, None]) == 1  # NULL A with n > 0
+    assert call([10, 20], [2, 0], [10, 20], ptrs=[A.value, None]) == 1  # n = 0 may be NULL: only the handle fails
+    assert call([10, 20], [2, 30], [10, 20]) == 4                     # m < n
+    assert call([100], [65], [100]) == 4                              # n > 64
+    assert call([100], [8], [100], dt=caqr.F32) == 4                  # FP32 not built
+    assert call([100], [8], [100], dt=7) == 1                         # unknown dtype
+    bad = caqr.TreeOpts(100, 0, 0, 0)
+    assert call([100], [8], [100], opts=ctypes.byref(bad)) == 1       # leaf_rows not 64/128/256
+    assert call([100, 300], [8, 64], [100, 300]) == 1                 # valid: NULL handle
+    assert call([], [], [], batch=0) == 1                             # empty batch, NULL handle
+    assert lib.caqr_batch_destroy(None) == 0
+    assert lib.caqr_batch_get_plan(None, 0, None) == 1
+    assert lib.caqr_batch_get_signs(None, 0, None) == 1
+    assert lib.caqr_tune_batched(None, caqr.F64) == 1
+    assert lib.caqr_batch_plan_for(None, 100, 8, caqr.F64, None) == 1
