@@ -26,12 +26,24 @@ constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
 constexpr int kDppRowHalfMirror = 0x141;  // lane r <-> 7 - r within each 8
 constexpr int kDppRowMirror = 0x140;      // lane r <-> 15 - r within each 16
 
+// Every pattern used here reads a lane of the same row, so every lane is
+// written and the move needs no "old" value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
   int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
+}
+
+// 1/x from the hardware estimate refined by two Newton steps (within about
+// one ulp; used only where x is a normal number well inside the range).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
 // Sum over the 16 lanes of a DPP row.  Every lane of the row ends with the

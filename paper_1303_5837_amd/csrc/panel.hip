@@ -66,16 +66,17 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
       const int par = j & 1;
       if (c == cj) {
         // ---- owner DPP row: reflector of column j (slot Q of this thread)
-        double sig = 0.0;
+        // sum of squares below the diagonal: four partial sums (short chain)
+        double sp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < NACT; ++i) {
           const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
           if (!act) continue;
           const bool below = (i > Q) || (r > cj);
           const double e = a[i][Q];
-          sig = below ? fma(e, e, sig) : sig;
+          sp[i & 3] = below ? fma(e, e, sp[i & 3]) : sp[i & 3];
         }
-        sig = row16_sum(sig);
+        double sig = row16_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
         const double alpha = readlane_f64(a[Q][Q], (cj & 3) * 16 + cj);
         const double s2 = fma(alpha, alpha, sig);
         // The reflector is formed from x scaled by 2^sh: sh = 0 normally; when
@@ -123,7 +124,10 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
         } else {
           const double beta_s = -copysign(mu_s, alpha_s);
           tau = (beta_s - alpha_s) / beta_s;
-          scal = 1.0 / (alpha_s - beta_s);
+          // |alpha - beta| = |alpha| + mu lies in [mu, 2 mu], a normal number:
+          // its reciprocal from the hardware estimate refined by two Newton
+          // steps, independent of the division above so that the two overlap
+          scal = rcp_nr(alpha_s - beta_s);
           beta = ldexp(beta_s, -sh);
         }
 #pragma unroll
@@ -132,7 +136,7 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
           if (!act) continue;
           double vv;
           if (i > Q || r > cj) {
-            vv = ldexp(a[i][Q], sh) * scal;
+            vv = (sh == 0 ? a[i][Q] : ldexp(a[i][Q], sh)) * scal;
             a[i][Q] = vv;
           } else if (r == cj && i == Q) {
             vv = 1.0;
@@ -153,9 +157,9 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
       // Slots whose columns are all finished (q < Q) are skipped.
       const double tau = sm.tau[par];
       const double *vrow = sm.v[par] + r;
-      double p[NQ];
+      double p[2][NQ];  // two partial sums per slot (half the dependency chain)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) p[q] = 0.0;
+      for (int q = 0; q < NQ; ++q) p[0][q] = p[1][q] = 0.0;
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
         const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
@@ -164,14 +168,14 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (q < Q) continue;
-          p[q] = fma(vi, a[i][q], p[q]);
+          p[i & 1][q] = fma(vi, a[i][q], p[i & 1][q]);
         }
       }
       double coef[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (q < Q) continue;
-        const double w = row16_sum(p[q]);
+        const double w = row16_sum(p[0][q] + p[1][q]);
         const int col = c + 16 * q;
         coef[q] = (col > j && col < b) ? tau * w : 0.0;
       }
