@@ -7,7 +7,7 @@
 namespace caqr {
 
 // Columns of C per workgroup of the update kernels (tickets are per tile).
-constexpr int kUpdTile = 64;
+constexpr int kUpdTile = 32;
 
 // One panel of the factorization: rows [0, m) x columns [0, b) at A (lda).
 struct PanelParams {

@@ -11,15 +11,18 @@
 //   node   (top b rows of the two leaves): W = C_1 + V^T C_2,  W <- T^T W,
 //                                          C_1 -= W,  C_2 -= V W
 //
-// (T instead of T^T for Q C.)  One workgroup updates the rows of a group of
-// leaves on one 64-column tile; wave w owns columns 16w..16w+15 of the tile
-// over all rows of a leaf and keeps them in registers between the two
-// products, so C is read and written once per leaf and no partial sums cross
-// waves.  The reflectors are staged through LDS in 64x64 blocks
-// (double-buffered, loaded with coalesced 16-byte accesses), and T goes
-// through the same buffers.  For Q^T the tree levels that lie inside a group
-// follow in the same launch; the levels above the groups run one launch per
-// level, so no workgroup ever waits for another.
+// (T instead of T^T for Q C.)  One workgroup of four waves updates the rows
+// of one leaf on one 32-column tile: wave (cg, rh) owns columns
+// 16cg..16cg+15 of the tile over row half rh of a leaf and keeps them in
+// registers between the two products, so C is read and written once per
+// leaf; the two halves add their partial W = Y^T C through LDS in a fixed
+// order.  Two workgroups share each CU (registers and LDS are sized for it),
+// so one issues MFMAs while the other waits for memory or a barrier.  The reflectors are staged through LDS in 64x64 blocks
+// (32 rows of each half, double-buffered, loaded with coalesced 16-byte
+// accesses), and T goes through the same buffers.  The tree levels run one
+// launch per level (nodes of a level and tiles in parallel), so no workgroup
+// ever waits for another; only the single-tile update of the next panel's
+// columns climbs the tree inside one launch, with tickets.
 //
 // Register layout ("contiguous"): a 16-row slab x of a tile is an f64x4 per
 // lane holding rows 16x + 4*(lane/16) + r, r = 0..3, of column lane%16.  The
@@ -34,10 +37,17 @@ namespace caqr {
 
 namespace {
 
+constexpr int kUThreads = 256;  // four waves: wave = column group cg (0..1) + 2 * row half rh
+
 struct UpdSmem {
-  alignas(16) double buf[2][kMaxB * kLdb];
-  int flag;
+  alignas(32) double buf[2][kMaxB * kLdb];  // reflector chunks, V, T; a free one holds the W partials
 };
+
+// Partial W of (row half, column group, block, lane) in a free staging buffer
+// (2 x 2 x 4 x 64 f64x4 = 32 KiB fits in one).
+__device__ __forceinline__ f64x4 *xch_at(double *buf, int rh, int cg, int a, int lane) {
+  return reinterpret_cast<f64x4 *>(buf) + ((rh * 2 + cg) * 4 + a) * 64 + lane;
+}
 
 __device__ __forceinline__ int pi16(int li) { return 4 * (li & 3) + (li >> 2); }
 
@@ -70,6 +80,17 @@ __device__ __forceinline__ void store_slab(double *C, int64_t ldc, int64_t grow,
     if (grow + q < m) C[grow + q + col * ldc] = v[q];
 }
 
+__device__ __forceinline__ f64x4 ld_c4(const double *p) {
+  const f64x2 lo = *reinterpret_cast<const f64x2 *>(p);
+  const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 2);
+  return f64x4{lo.x, lo.y, hi.x, hi.y};
+}
+
+__device__ __forceinline__ void st_c4(double *p, f64x4 v) {
+  *reinterpret_cast<f64x2 *>(p) = f64x2{v[0], v[1]};
+  *reinterpret_cast<f64x2 *>(p + 2) = f64x2{v[2], v[3]};
+}
+
 // W <- T^T W (TRANS) or T W, in place, with T staged in LDS (64x64, ld kLdb);
 // W in the contiguous layout (slab a = reflectors 16a..16a+15).  Block ao of
 // T^T W needs blocks a <= ao of W, so the blocks are produced from the last
@@ -95,66 +116,100 @@ __device__ __forceinline__ void apply_t_lds(const double *Ts, f64x4 (&w)[NQ]) {
   }
 }
 
+// The two row halves of a column group hold partial sums of W; afterwards
+// both hold W = P(half 0) + P(half 1), added in the same order (bitwise equal).
+// xbuf is a free staging buffer; ends with the partials read, so the caller's
+// next barrier frees it again.
+template <int NQ>
+__device__ __forceinline__ void exchange_w(f64x4 (&w)[NQ], double *xbuf) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int cg = wave & 1, rh = wave >> 1;
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) *xch_at(xbuf, rh, cg, a, lane) = w[a];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) w[a] = *xch_at(xbuf, 0, cg, a, lane) + *xch_at(xbuf, 1, cg, a, lane);
+}
+
 // Update of the top b rows of tree node `node` (eliminated leaf) and of its
-// left sibling on this workgroup's tile.  Wave w holds all 16*NQ top rows of
-// both row blocks for columns 16w..16w+15, so W = C1 + V^T C2 is complete in
-// every wave.  V goes to LDS buffer 0 and T to buffer 1.
+// left sibling on this workgroup's tile.  Wave (cg, rh) holds slabs 2rh and
+// 2rh + 1 (16 rows each) of both row blocks for columns 16cg..16cg+15; the two
+// halves form W = C1 + V^T C2 from partial sums.  V goes to LDS buffer 0;
+// buffer 1 first holds the partial sums, then T.
 template <int NQ, bool TRANS>
 __device__ __forceinline__ void node_update(const UpdateParams &u, int left, int node, int tile, UpdSmem &sm,
                                             bool vec_ok) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int cg = wave & 1, rh = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
   const int pl = pi16(li);
-  const int64_t col = (int64_t)tile * kUpdTile + 16 * wave + li;
+  const int64_t col = (int64_t)tile * kUpdTile + 16 * cg + li;
   const bool colok = col < u.k;
   const int64_t r1 = (int64_t)left * u.h, r2 = (int64_t)node * u.h;
   const int64_t m1 = min<int64_t>(u.m, r1 + u.b), m2 = min<int64_t>(u.m, r2 + u.b);
-  Stage st;
-  stage_load<kNodeV>(st, u.Y, u.ldy, r2, r2, u.m, u.b, vec_ok, tid);
-  stage_fix<kNodeV>(st, 0, tid);
-  stage_store(st, sm.buf[0], tid);
-  stage_load<kDense>(st, u.T_node + (int64_t)node * 64 * 64, 64, 0, 0, 0, 0, true, tid);
-  stage_store(st, sm.buf[1], tid);
-  f64x4 c1[NQ], c2[NQ];
+  StageSplit<kUThreads> st;
+  stage_load_split<kNodeV>(st, u.Y, u.ldy, r2, r2 + 32, 0, 32, u.m, u.b, vec_ok, tid);
+  stage_fix_split<kNodeV>(st, 0, 32, tid);
+  stage_store_split(st, sm.buf[0], tid);
+  stage_load_split<kDense>(st, u.T_node + (int64_t)node * 64 * 64, 64, 0, 0, 0, 0, 0, 0, true, tid);
+  f64x4 c1[2], c2[2];
 #pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    c1[t] = load_slab(u.C, u.ldc, r1 + 16 * t + 4 * lk, col, m1, colok, vec_ok);
-    c2[t] = load_slab(u.C, u.ldc, r2 + 16 * t + 4 * lk, col, m2, colok, vec_ok);
+  for (int x = 0; x < 2; ++x) {
+    const int t = 2 * rh + x;
+    if (t < NQ) {
+      c1[x] = load_slab(u.C, u.ldc, r1 + 16 * t + 4 * lk, col, m1, colok, vec_ok);
+      c2[x] = load_slab(u.C, u.ldc, r2 + 16 * t + 4 * lk, col, m2, colok, vec_ok);
+    }
   }
   __syncthreads();
-  // W = C1 + V^T C2 (V upper triangular: slab t reaches blocks a >= t)
+  // partial W over this wave's slabs: its own slabs of C1 plus V(slab)^T C2(slab)
   f64x4 w[NQ];
 #pragma unroll
   for (int a = 0; a < NQ; ++a) {
-    f64x4 acc = c1[a];
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t <= a; ++t) {
+    for (int x = 0; x < 2; ++x) {
+      const int t = 2 * rh + x;
+      if (t > a) continue;  // V upper triangular (also skips t >= NQ)
       const f64x4 v = lds_col4(sm.buf[0], 16 * a + pl, 16 * t + 4 * lk);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc = mfma16x16x4(v[r], c2[t][r], acc);
+      for (int r = 0; r < 4; ++r) acc = mfma16x16x4(v[r], c2[x][r], acc);
+      if (t == a) acc += c1[x];
     }
     w[a] = acc;
   }
+  exchange_w<NQ>(w, sm.buf[1]);
+  __syncthreads();  // partials read: buffer 1 takes T
+  stage_store_split(st, sm.buf[1], tid);
+  __syncthreads();
   apply_t_lds<NQ, TRANS>(sm.buf[1], w);
   // C1 -= W';  C2 -= V W'
 #pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    c1[t] -= w[t];
-    f64x4 acc = c2[t];
+  for (int x = 0; x < 2; ++x) {
+    const int t = 2 * rh + x;
+    if (t >= NQ) continue;
 #pragma unroll
-    for (int a = t; a < NQ; ++a) {
+    for (int a = 0; a < NQ; ++a)
+      if (a == t) c1[x] -= w[a];
+    f64x4 acc = c2[x];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+      if (a < t) continue;
       const f64x4 v = lds_row4(sm.buf[0], 16 * t + pl, 16 * a + 4 * lk);
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc = mfma16x16x4(-v[r], w[a][r], acc);
     }
-    c2[t] = acc;
+    c2[x] = acc;
   }
 #pragma unroll
-  for (int t = 0; t < NQ; ++t) {
-    store_slab(u.C, u.ldc, r1 + 16 * t + 4 * lk, col, m1, colok, vec_ok, c1[t]);
-    store_slab(u.C, u.ldc, r2 + 16 * t + 4 * lk, col, m2, colok, vec_ok, c2[t]);
+  for (int x = 0; x < 2; ++x) {
+    const int t = 2 * rh + x;
+    if (t >= NQ) continue;
+    store_slab(u.C, u.ldc, r1 + 16 * t + 4 * lk, col, m1, colok, vec_ok, c1[x]);
+    store_slab(u.C, u.ldc, r2 + 16 * t + 4 * lk, col, m2, colok, vec_ok, c2[x]);
   }
   __syncthreads();  // LDS buffers free again
 }
@@ -162,7 +217,7 @@ __device__ __forceinline__ void node_update(const UpdateParams &u, int left, int
 // Rows 0..b-1 of this workgroup's tile scaled by D (any thread mapping; the
 // caller orders it after the tile's last update).
 __device__ __forceinline__ void scale_top_rows(const UpdateParams &u, int tile) {
-  for (int e = threadIdx.x; e < u.b * kUpdTile; e += kThreads) {
+  for (int e = threadIdx.x; e < u.b * kUpdTile; e += blockDim.x) {
     const int row = e % u.b;
     const int64_t col = (int64_t)tile * kUpdTile + e / u.b;
     if (col < u.k && row < u.m) u.C[row + col * u.ldc] *= u.d[row];
@@ -170,223 +225,165 @@ __device__ __forceinline__ void scale_top_rows(const UpdateParams &u, int tile) 
 }
 
 // Rows 0..b-1 scaled by D, each lane on the rows it wrote itself in
-// node_update / leaf_update (rows 16t + 4(lane/16) + r of column lane%16).
+// node_update (or in leaf_update of leaf 0's first slabs): rows
+// 16t + 4(lane/16) + r, t = 2rh + x, of column lane%16 of its column group.
 template <int NQ>
 __device__ __forceinline__ void scale_top_rows_own(const UpdateParams &u, int tile) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const int cg = wave & 1, rh = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t col = (int64_t)tile * kUpdTile + 16 * wave + li;
+  const int64_t col = (int64_t)tile * kUpdTile + 16 * cg + li;
   if (col >= u.k) return;
 #pragma unroll
-  for (int t = 0; t < NQ; ++t)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * t + 4 * lk + r;
+      const int row = 16 * (2 * rh + x) + 4 * lk + r;
       if (row < u.b && row < u.m) u.C[row + col * u.ldc] *= u.d[row];
     }
 }
 
-// Whether the whole leaf x tile block of C is in range and 16-byte aligned
-// (uniform fast path for C).
-__device__ __forceinline__ bool leaf_cfast(const UpdateParams &u, int leaf, int tile) {
-  return aligned16(u.C) && (u.ldc % 2 == 0) && (int64_t)(leaf + 1) * u.h <= u.m &&
-         (int64_t)(tile + 1) * kUpdTile <= u.k;
-}
-
-__device__ __forceinline__ f64x4 ld_c4(const double *p) {
-  const f64x2 lo = *reinterpret_cast<const f64x2 *>(p);
-  const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 2);
-  return f64x4{lo.x, lo.y, hi.x, hi.y};
-}
-
-__device__ __forceinline__ void st_c4(double *p, f64x4 v) {
-  *reinterpret_cast<f64x2 *>(p) = f64x2{v[0], v[1]};
-  *reinterpret_cast<f64x2 *>(p + 2) = f64x2{v[2], v[3]};
-}
-
 // Q^T (TRANS) or Q update of one leaf on one tile: C_leaf <- C_leaf - Y (T^T (Y^T C_leaf)).
-// Wave w holds all H rows of the leaf for columns 16w..16w+15 in registers
-// (RT slabs of 16 rows), so both products are complete inside the wave.  The
-// reflectors go through LDS in 64-row chunks, double-buffered: chunks 0..n-1
-// for W = Y^T C, then T, then chunks n-1..0 for C -= Y W' (the last chunk of
-// the first pass is still in LDS and is not reloaded).  Chunk c always sits in
-// buffer c % 2; T sits in buffer n % 2.  Inside a chunk the LDS operands of
-// the next 16-row slab are read before the products of the current one.
-// Every chunk of C is stored as soon as it is final.  `pre` carries the first
-// 64 rows of this leaf's tile when the previous call prefetched them
-// (has_pre); with next >= 0 this call prefetches those rows of leaf `next`
-// during its second pass.
+// Wave (cg, rh) holds rows rh*H/2 .. rh*H/2 + H/2 - 1 of the leaf for columns
+// 16cg..16cg+15 in registers (RT/2 slabs of 16 rows).  Reflector chunk c holds
+// 32 rows of each half (block rows 0..31: half 0 rows 32c.., 32..63: half 1),
+// so every wave works on every chunk.  Chunks 0..n-1 for W = Y^T C, then T,
+// then chunks n-1..0 for C -= Y W'; chunk c sits in buffer c % 2, T in buffer
+// n % 2, and the W partials are exchanged in the last chunk's buffer.
+// Every chunk of C is stored as soon as it is final.
 template <int NQ, int RT, bool TRANS>
-__device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int tile, UpdSmem &sm, f64x4 (&pre)[4],
-                                            bool has_pre, int next) {
+__device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int tile, UpdSmem &sm) {
   constexpr int H = 16 * RT;       // leaf rows
-  constexpr int NCHUNK = H / 64;   // 64-row chunks
+  constexpr int HALF = H / 2;      // rows per wave
+  constexpr int NX = RT / 2;       // 16-row slabs per wave
+  constexpr int NCHUNK = HALF / 32;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int cg = wave & 1, rh = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
   const int pl = pi16(li);
   const int64_t row0 = (int64_t)leaf * u.h;
-  const int64_t col = (int64_t)tile * kUpdTile + 16 * wave + li;
+  const int64_t col = (int64_t)tile * kUpdTile + 16 * cg + li;
   const bool colok = col < u.k;
   const bool vec_c = aligned16(u.C) && (u.ldc % 2 == 0);
   const bool vec_y = aligned16(u.Y) && (u.ldy % 2 == 0);
+  const int xl0 = rh * NX;  // leaf slab index of this wave's slab 0
 
-  Stage st;
-  stage_load<kLeafY>(st, u.Y, u.ldy, row0, row0, u.m, u.b, vec_y, tid);
-  const bool cfast = leaf_cfast(u, leaf, tile);
-  double *cptr = u.C + row0 + 4 * lk + col * u.ldc;
-  f64x4 acc[RT];  // rows row0 + 16x + 4lk + r
+  StageSplit<kUThreads> st;
+  stage_load_split<kLeafY>(st, u.Y, u.ldy, row0, row0 + HALF, 0, HALF, u.m, u.b, vec_y, tid);
+  // uniform fast path for C: the whole leaf x tile block in range and aligned
+  const bool cfast = vec_c && row0 + H <= u.m && (int64_t)(tile + 1) * kUpdTile <= u.k;
+  double *cptr = u.C + row0 + rh * HALF + 4 * lk + col * u.ldc;
+  f64x4 acc[NX];  // rows row0 + rh*HALF + 16x + 4lk + r
   if (cfast) {
 #pragma unroll
-    for (int x = 0; x < RT; ++x) {
-      if (x < 4 && has_pre)
-        acc[x] = pre[x];
-      else
-        acc[x] = ld_c4(cptr + 16 * x);
-    }
+    for (int x = 0; x < NX; ++x) acc[x] = ld_c4(cptr + 16 * x);
   } else {
 #pragma unroll
-    for (int x = 0; x < RT; ++x) acc[x] = load_slab(u.C, u.ldc, row0 + 16 * x + 4 * lk, col, u.m, colok, vec_c);
+    for (int x = 0; x < NX; ++x)
+      acc[x] = load_slab(u.C, u.ldc, row0 + rh * HALF + 16 * x + 4 * lk, col, u.m, colok, vec_c);
   }
-  stage_fix<kLeafY>(st, 0, tid);
-  stage_store(st, sm.buf[0], tid);
+  stage_fix_split<kLeafY>(st, 0, HALF, tid);
+  stage_store_split(st, sm.buf[0], tid);
   __syncthreads();
 
-  // ---- W = Y^T C, chunk by chunk
+  // ---- partial W = Y^T C over this wave's rows, chunk by chunk
   f64x4 w[NQ];
 #pragma unroll
   for (int a = 0; a < NQ; ++a) w[a] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < NCHUNK; ++c) {
     if (c + 1 < NCHUNK)
-      stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (c + 1), row0, u.m, u.b, vec_y, tid);
+      stage_load_split<kLeafY>(st, u.Y, u.ldy, row0 + 32 * (c + 1), row0 + HALF + 32 * (c + 1), 32 * (c + 1),
+                               HALF + 32 * (c + 1), u.m, u.b, vec_y, tid);
     else
-      stage_load<kDense>(st, u.T_leaf + (int64_t)leaf * 64 * 64, 64, 0, 0, 0, 0, true, tid);
+      stage_load_split<kDense>(st, u.T_leaf + (int64_t)leaf * 64 * 64, 64, 0, 0, 0, 0, 0, 0, true, tid);
     const double *ys = sm.buf[c & 1];
-    f64x4 y[2][NQ];
 #pragma unroll
-    for (int a = 0; a < NQ; ++a)
-      if (4 * c >= a) y[0][a] = lds_col4(ys, 16 * a + pl, 4 * lk);
+    for (int tt = 0; tt < 2; ++tt) {
+      const int x = 2 * c + tt;
+      const int xl = xl0 + x;  // slab index within the leaf
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const int x = 4 * c + tt;  // slab index within the leaf
-      if (tt + 1 < 4) {
+      for (int a = 0; a < NQ; ++a) {
+        if (xl < a) continue;  // rows above block a are zero
+        const f64x4 y = lds_col4(ys, 16 * a + pl, 32 * rh + 16 * tt + 4 * lk);
 #pragma unroll
-        for (int a = 0; a < NQ; ++a)
-          if (x + 1 >= a) y[(tt + 1) & 1][a] = lds_col4(ys, 16 * a + pl, 16 * (tt + 1) + 4 * lk);
+        for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(y[r], acc[x][r], w[a]);
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int a = 0; a < NQ; ++a)
-          if (x >= a) w[a] = mfma16x16x4(y[tt & 1][a][r], acc[x][r], w[a]);  // rows above block a are zero
     }
-    stage_store(st, sm.buf[(c + 1) & 1], tid);
+    if (c + 1 < NCHUNK && 32 * (c + 1) < kMaxB)  // rows of the leaf's top triangle
+      stage_fix_split<kLeafY>(st, 32 * (c + 1), HALF + 32 * (c + 1), tid);
+    stage_store_split(st, sm.buf[(c + 1) & 1], tid);
     __syncthreads();
   }
-  // ---- W' = -T^T W (T in buffer NCHUNK % 2); the next chunk of the second
-  // pass (NCHUNK - 2) is loaded meanwhile and goes into T's buffer afterwards
-  if (NCHUNK > 1) stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (NCHUNK - 2), row0, u.m, u.b, vec_y, tid);
+  // ---- W = P(half 0) + P(half 1), exchanged in the buffer of the last chunk
+  // (reloaded below); W' = -T^T W (T in buffer NCHUNK % 2).  The last chunk is
+  // loaded again meanwhile for the second pass.
+  stage_load_split<kLeafY>(st, u.Y, u.ldy, row0 + 32 * (NCHUNK - 1), row0 + HALF + 32 * (NCHUNK - 1),
+                           32 * (NCHUNK - 1), HALF + 32 * (NCHUNK - 1), u.m, u.b, vec_y, tid);
+  exchange_w<NQ>(w, sm.buf[(NCHUNK - 1) & 1]);
   apply_t_lds<NQ, TRANS>(sm.buf[NCHUNK & 1], w);
 #pragma unroll
   for (int a = 0; a < NQ; ++a) w[a] = -w[a];
-  if (next >= 0) {  // first 64 rows of the next leaf's tile (fast path; the caller checked)
-    const double *np = u.C + (int64_t)next * u.h + 4 * lk + col * u.ldc;
-#pragma unroll
-    for (int x = 0; x < 4; ++x) pre[x] = ld_c4(np + 16 * x);
-  }
+  __syncthreads();  // partials read, T used: both buffers free
+  if (32 * (NCHUNK - 1) < kMaxB) stage_fix_split<kLeafY>(st, 32 * (NCHUNK - 1), HALF + 32 * (NCHUNK - 1), tid);
+  stage_store_split(st, sm.buf[(NCHUNK - 1) & 1], tid);
+  if (NCHUNK > 1)
+    stage_load_split<kLeafY>(st, u.Y, u.ldy, row0 + 32 * (NCHUNK - 2), row0 + HALF + 32 * (NCHUNK - 2),
+                             32 * (NCHUNK - 2), HALF + 32 * (NCHUNK - 2), u.m, u.b, vec_y, tid);
   __syncthreads();
   // ---- C += Y W', chunks NCHUNK-1 .. 0
 #pragma unroll
   for (int c = NCHUNK - 1; c >= 0; --c) {
     if (c >= 1) {
-      if (c == 1) stage_fix<kLeafY>(st, 0, tid);   // chunk 0 holds the diagonal
-      stage_store(st, sm.buf[(c - 1) & 1], tid);  // chunk c - 1 into the buffer chunk c + 1 (or T) left
-      if (c >= 2) stage_load<kLeafY>(st, u.Y, u.ldy, row0 + 64 * (c - 2), row0, u.m, u.b, vec_y, tid);
+      if (32 * (c - 1) < kMaxB)  // rows of the leaf's top triangle
+        stage_fix_split<kLeafY>(st, 32 * (c - 1), HALF + 32 * (c - 1), tid);
+      stage_store_split(st, sm.buf[(c - 1) & 1], tid);  // into the buffer chunk c + 1 (or T) left
+      if (c >= 2)
+        stage_load_split<kLeafY>(st, u.Y, u.ldy, row0 + 32 * (c - 2), row0 + HALF + 32 * (c - 2), 32 * (c - 2),
+                                 HALF + 32 * (c - 2), u.m, u.b, vec_y, tid);
     }
     const double *ys = sm.buf[c & 1];
-    f64x4 y[2][NQ];
 #pragma unroll
-    for (int a = 0; a < NQ; ++a)
-      if (4 * c >= a) y[0][a] = lds_row4(ys, pl, 16 * a + 4 * lk);
+    for (int tt = 0; tt < 2; ++tt) {
+      const int x = 2 * c + tt;
+      const int xl = xl0 + x;
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const int x = 4 * c + tt;
-      if (tt + 1 < 4) {
+      for (int a = 0; a < NQ; ++a) {
+        if (xl < a) continue;
+        const f64x4 y = lds_row4(ys, 32 * rh + 16 * tt + pl, 16 * a + 4 * lk);
 #pragma unroll
-        for (int a = 0; a < NQ; ++a)
-          if (x + 1 >= a) y[(tt + 1) & 1][a] = lds_row4(ys, 16 * (tt + 1) + pl, 16 * a + 4 * lk);
+        for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(y[r], w[a][r], acc[x]);
       }
-#pragma unroll
-      for (int a = 0; a < NQ; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (x >= a) acc[x] = mfma16x16x4(y[tt & 1][a][r], w[a][r], acc[x]);
     }
     // rows of chunk c are final
-    if (cfast) {
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) st_c4(cptr + 16 * (4 * c + tt), acc[4 * c + tt]);
-    } else {
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
-        store_slab(u.C, u.ldc, row0 + 16 * (4 * c + tt) + 4 * lk, col, u.m, colok, vec_c, acc[4 * c + tt]);
+    for (int tt = 0; tt < 2; ++tt) {
+      const int x = 2 * c + tt;
+      if (cfast)
+        st_c4(cptr + 16 * x, acc[x]);
+      else
+        store_slab(u.C, u.ldc, row0 + rh * HALF + 16 * x + 4 * lk, col, u.m, colok, vec_c, acc[x]);
     }
     if (c >= 1) __syncthreads();
   }
   __syncthreads();  // LDS free for the next update
 }
 
-// One leaf update with no prefetch on either side.
+// Leaf updates of one panel, one workgroup per (leaf, tile): Q^T (TRANS) runs
+// them before the tree levels, Q after them.  No workgroup depends on another.
 template <int NQ, int RT, bool TRANS>
-__device__ __forceinline__ void leaf_update_single(const UpdateParams &u, int leaf, int tile, UpdSmem &sm) {
-  f64x4 pre[4];
-  leaf_update<NQ, RT, TRANS>(u, leaf, tile, sm, pre, false, -1);
-}
-
-// Q^T of one panel on one tile, for the leaves of group g (u.group leaves,
-// a power of two): every leaf update, then the tree levels that are complete
-// inside the group (binary pairs i, i + 2^(k-1), the lower index on top).  A
-// single group covers the whole tree and also applies D.  No workgroup
-// depends on another, so no device-scope synchronization is needed; the
-// levels above the groups run afterwards, one launch per level.
-template <int NQ, int RT>
-__global__ void __launch_bounds__(kThreads, 1) qt_group_kernel(UpdateParams u) {
-  __shared__ UpdSmem sm;
-  const int ngroups = (u.L + u.group - 1) / u.group;
-  const int g = blockIdx.x % ngroups;
-  const int tile = blockIdx.x / ngroups;
-  const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
-  const int first = g * u.group, last = min(u.L, first + u.group);
-  f64x4 pre[4];
-  bool has_pre = false;
-#pragma nounroll
-  for (int leaf = first; leaf < last; ++leaf) {
-    const int lf = __builtin_amdgcn_readfirstlane(leaf);
-    const int next = (lf + 1 < last && leaf_cfast(u, lf + 1, tile)) ? lf + 1 : -1;
-    leaf_update<NQ, RT, true>(u, lf, tile, sm, pre, has_pre, next);
-    has_pre = next >= 0;
-  }
-  for (int half = 1; half < u.group && half < u.L; half <<= 1)
-#pragma nounroll
-    for (int node = first + half; node < last; node += 2 * half)
-      node_update<NQ, true>(u, node - half, node, tile, sm, vec_ok);
-  if (ngroups == 1) scale_top_rows_own<NQ>(u, tile);
-}
-
-// Q applied (not transposed): leaves only, no tree (the tree runs first, top-down).
-template <int NQ, int RT>
-__global__ void __launch_bounds__(kThreads, 1) qn_leaf_kernel(UpdateParams u) {
+__global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
   const int leaf = blockIdx.x % u.L;
   const int tile = blockIdx.x / u.L;
-  leaf_update_single<NQ, RT, false>(u, leaf, tile, sm);
+  leaf_update<NQ, RT, TRANS>(u, leaf, tile, sm);
 }
 
 template <int NQ, bool TRANS>
-__global__ void __launch_bounds__(kThreads, 2) node_level_kernel(UpdateParams u) {
+__global__ void __launch_bounds__(kUThreads, 2) node_level_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
   // nodes of this level: ids half, 3*half, 5*half, ... < L
   const int half = 1 << (u.level - 1);
@@ -425,12 +422,12 @@ __device__ __forceinline__ bool arrive(unsigned *tickets, int node, int &flag) {
 // pairing is fixed by index, so the result does not depend on arrival order.
 // The workgroup that completes the root applies D.
 template <int NQ, int RT>
-__global__ void __launch_bounds__(kThreads, 1) qt_tree_tile_kernel(UpdateParams u) {
+__global__ void __launch_bounds__(kUThreads, 2) qt_tree_tile_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
   __shared__ int flag;
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
   const int leaf = blockIdx.x;
-  leaf_update_single<NQ, RT, true>(u, leaf, 0, sm);
+  leaf_update<NQ, RT, true>(u, leaf, 0, sm);
   int rt = leaf;  // root of the subtree this workgroup holds
   for (int half = 1; half < u.L; half <<= 1) {
     if ((rt & (2 * half - 1)) == 0) {  // left child at this level
@@ -451,30 +448,26 @@ __global__ void __launch_bounds__(kThreads, 1) qt_tree_tile_kernel(UpdateParams 
 template <int NQ, int RT>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   if (u.tickets && u.tiles == 1 && u.L > 1) {
-    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT>), dim3(u.L), dim3(kThreads), 0, s, u);
+    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT>), dim3(u.L), dim3(kUThreads), 0, s, u);
     return hipGetLastError();
   }
-  const int ngroups = (u.L + u.group - 1) / u.group;
-  hipLaunchKernelGGL((qt_group_kernel<NQ, RT>), dim3(ngroups * u.tiles), dim3(kThreads), 0, s, u);
-  if (ngroups > 1) {
-    // levels above the groups, one launch per level (nodes of a level in parallel), then D
-    int lev = 1;
-    while ((1 << (lev - 1)) < u.group) ++lev;
-    for (; (1 << (lev - 1)) < u.L; ++lev) {
-      UpdateParams v = u;
-      v.level = lev;
-      const int half = 1 << (lev - 1);
-      const int per = (u.L + half - 1) / (2 * half) + 1;
-      hipLaunchKernelGGL((node_level_kernel<NQ, true>), dim3(per * u.tiles), dim3(kThreads), 0, s, v);
-    }
-    hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kThreads), 0, s, u);
+  // leaves, then the tree bottom-up (one launch per level, nodes of a level in
+  // parallel), then D
+  hipLaunchKernelGGL((leaf_kernel<NQ, RT, true>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
+  for (int lev = 1; (1 << (lev - 1)) < u.L; ++lev) {
+    UpdateParams v = u;
+    v.level = lev;
+    const int half = 1 << (lev - 1);
+    const int per = (u.L + half - 1) / (2 * half) + 1;
+    hipLaunchKernelGGL((node_level_kernel<NQ, true>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
   }
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
   return hipGetLastError();
 }
 
 template <int NQ, int RT>
 hipError_t launch_qn_t(const UpdateParams &u, hipStream_t s) {
-  hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kThreads), 0, s, u);
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
   int levels = 0;
   while ((1 << levels) < u.L) ++levels;
   for (int lev = levels; lev >= 1; --lev) {
@@ -482,9 +475,9 @@ hipError_t launch_qn_t(const UpdateParams &u, hipStream_t s) {
     v.level = lev;
     const int half = 1 << (lev - 1);
     const int per = (u.L + half - 1) / (2 * half) + 1;
-    hipLaunchKernelGGL((node_level_kernel<NQ, false>), dim3(per * u.tiles), dim3(kThreads), 0, s, v);
+    hipLaunchKernelGGL((node_level_kernel<NQ, false>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
   }
-  hipLaunchKernelGGL((qn_leaf_kernel<NQ, RT>), dim3(u.L * u.tiles), dim3(kThreads), 0, s, u);
+  hipLaunchKernelGGL((leaf_kernel<NQ, RT, false>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
   return hipGetLastError();
 }
 
