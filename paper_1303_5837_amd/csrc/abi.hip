@@ -289,11 +289,6 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
   u.T_node = p.T_node;
   u.d = p.d;
   u.tiles = ceil_div(k, kUpdTile);
-  // leaves per workgroup: the smallest power of two that keeps the grid
-  // within about two workgroups per CU (one resident at a time, 256 CUs)
-  int g = 1;
-  while (g < p.L && (int64_t)ceil_div(p.L, g) * u.tiles > 512) g <<= 1;
-  u.group = g;
   u.level = 0;
   u.tickets = nullptr;
   return u;
@@ -361,8 +356,8 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
 // launch is ordered by stream order or by an event, and all work ends on the
 // handle's stream.
 caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) {
-  size_t need = 0;
-  for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L);
+  size_t need = 0;  // panel trees, and the tile trees of the next panel's update
+  for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L * kTreeTiles);
   caqr_status_t st = ensure_tickets(h, need);
   if (st) return st;
   const int P = (int)F->panels.size();

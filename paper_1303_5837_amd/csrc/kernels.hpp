@@ -6,8 +6,11 @@
 
 namespace caqr {
 
-// Columns of C per workgroup of the update kernels (tickets are per tile).
+// Columns of C per workgroup of the update kernels.
 constexpr int kUpdTile = 32;
+// Updates of at most this many tiles climb the tree inside one launch (with
+// tickets, L per tile); wider ones run one launch per tree level.
+constexpr int kTreeTiles = 4;
 
 // One panel of the factorization: rows [0, m) x columns [0, b) at A (lda).
 struct PanelParams {
@@ -39,10 +42,10 @@ struct UpdateParams {
   const double *T_node;
   const double *d;    // signs
   int tiles;          // column tiles of kUpdTile
-  int group;          // leaves per workgroup of the Q^T kernel (power of two)
   int level;          // node kernels: tree level processed (half = 1 << (level-1))
-  unsigned *tickets;  // [L] zero on entry and exit, or null; with tickets, a
-                      // single-tile Q^T runs the whole tree in one launch
+  unsigned *tickets;  // [kTreeTiles * L] zero on entry and exit, or null; with
+                      // tickets, a Q^T of at most kTreeTiles tiles runs the
+                      // whole tree in one launch
 };
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s);
@@ -54,9 +57,9 @@ hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items
                                      hipStream_t s);
 
 // C <- Q^T C for one panel: leaf updates and the tree bottom-up, then rows
-// 0..b-1 scaled by D.  One workgroup per (group of u.group leaves, tile) runs
-// the leaves and the tree levels inside its group; a second launch runs the
-// levels above the groups.
+// 0..b-1 scaled by D.  One workgroup per (leaf, tile), then one launch per
+// tree level; with tickets and at most kTreeTiles tiles, one launch in which
+// each (leaf, tile) workgroup climbs its tile's tree.
 hipError_t launch_apply_qt(const UpdateParams &u, hipStream_t s);
 
 // C <- Q C for one panel: rows 0..b-1 scaled by D, the tree top-down (one

@@ -415,9 +415,9 @@ __device__ __forceinline__ bool arrive(unsigned *tickets, int node, int &flag) {
   return second;
 }
 
-// Q^T of one panel on a single tile (at most 64 columns, e.g. the next
-// panel's), the whole tree in one launch: workgroup i updates leaf i, then
-// climbs the binary tree; below every node the second workgroup to arrive (an
+// Q^T of one panel on a few tiles (at most kTreeTiles, e.g. the next panel's
+// columns), the whole tree in one launch: workgroup (leaf i, tile t) updates
+// leaf i on tile t, then climbs that tile's binary tree; below every node the second workgroup to arrive (an
 // agent-scope ticket) performs the node's update, the first one exits.  The
 // pairing is fixed by index, so the result does not depend on arrival order.
 // The workgroup that completes the root applies D.
@@ -426,29 +426,31 @@ __global__ void __launch_bounds__(kUThreads, 2) qt_tree_tile_kernel(UpdateParams
   __shared__ UpdSmem sm;
   __shared__ int flag;
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
-  const int leaf = blockIdx.x;
-  leaf_update<NQ, RT, true>(u, leaf, 0, sm);
+  const int leaf = blockIdx.x % u.L;
+  const int tile = blockIdx.x / u.L;
+  unsigned *tickets = u.tickets + (int64_t)tile * u.L;  // each tile climbs its own tree
+  leaf_update<NQ, RT, true>(u, leaf, tile, sm);
   int rt = leaf;  // root of the subtree this workgroup holds
   for (int half = 1; half < u.L; half <<= 1) {
     if ((rt & (2 * half - 1)) == 0) {  // left child at this level
       const int partner = rt + half;
       if (partner >= u.L) continue;      // no sibling: pass through
-      if (!arrive(u.tickets, partner, flag)) return;
-      node_update<NQ, true>(u, rt, partner, 0, sm, vec_ok);
+      if (!arrive(tickets, partner, flag)) return;
+      node_update<NQ, true>(u, rt, partner, tile, sm, vec_ok);
     } else {  // right child: node id rt, left sibling rt - half
       const int left = rt - half;
-      if (!arrive(u.tickets, rt, flag)) return;
-      node_update<NQ, true>(u, left, rt, 0, sm, vec_ok);
+      if (!arrive(tickets, rt, flag)) return;
+      node_update<NQ, true>(u, left, rt, tile, sm, vec_ok);
       rt = left;
     }
   }
-  scale_top_rows_own<NQ>(u, 0);
+  scale_top_rows_own<NQ>(u, tile);
 }
 
 template <int NQ, int RT>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
-  if (u.tickets && u.tiles == 1 && u.L > 1) {
-    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT>), dim3(u.L), dim3(kUThreads), 0, s, u);
+  if (u.tickets && u.tiles <= kTreeTiles && u.L > 1) {
+    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
     return hipGetLastError();
   }
   // leaves, then the tree bottom-up (one launch per level, nodes of a level in
