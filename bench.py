@@ -68,6 +68,58 @@ def panel_bytes(rows: int, b: int) -> float:
     return 16.0 * rows * b
 
 
+def batched_line(dtype_name: str):
+    """The uneven 2000-problem batch in one element type (float: the double draws
+    rounded), tuned first; median of 10 timed tsqr_factor_batched calls."""
+    import numpy as np
+    import torch
+
+    from paper_1303_5837_amd import caqr, inputs
+
+    dtype = {"f64": torch.float64, "f32": torch.float32}[dtype_name]
+    ms, ns = inputs.batched_tsqr_sizes()
+    seed = inputs.SEEDS["batched_tsqr"]
+    P = [inputs.gaussian_device(int(m), int(n), seed * 100003 + i).to(dtype) for i, (m, n) in enumerate(zip(ms, ns))]
+    P = [a.t().contiguous().t() for a in P]
+    W = [torch.empty_like(a.t()).t() for a in P]
+    t_tune = time.perf_counter()
+    caqr.tune_batched(dtype=dtype)
+    t_tune = time.perf_counter() - t_tune
+    times = []
+    for it in range(3 + 10):
+        for w, a in zip(W, P):
+            w.copy_(a)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        Bt = caqr.tsqr_batched(W)
+        e1.record()
+        torch.cuda.synchronize()
+        if it >= 3:
+            times.append(e0.elapsed_time(e1))
+        Bt.close()
+    t = float(np.median(times))
+    es = 8 if dtype == torch.float64 else 4
+    alg = float(sum(2.0 * es * int(m) * int(n) for m, n in zip(ms, ns)))  # read A, write R and Y
+    flops = float(sum(2.0 * int(m) * int(n) ** 2 - 2.0 * int(n) ** 3 / 3 for m, n in zip(ms, ns)))
+    plans = {}
+    for m, n in zip(ms, ns):
+        k = "h%d/lpw%d" % caqr.batch_plan_for(int(m), int(n), dtype=dtype)
+        plans[k] = plans.get(k, 0) + 1
+    del P, W
+    torch.cuda.empty_cache()
+    return {
+        "dtype": dtype_name,
+        "median_ms": round(t, 4), "p10_ms": round(float(np.percentile(times, 10)), 4),
+        "p90_ms": round(float(np.percentile(times, 90)), 4),
+        "matrices_per_s": round(len(ms) / (t * 1e-3), 1), "gflops": round(flops / (t * 1e-3) / 1e9, 1),
+        "algorithmic_GBps": round(alg / (t * 1e-3) / 1e9, 1),
+        "pct_hbm_peak": round(100 * alg / (t * 1e-3) / 1e9 / PEAK_HBM_GBS, 2),
+        "bytes": alg, "tune_s": round(t_tune, 2), "plans": plans,
+        "timed": "one tsqr_factor_batched call incl. planning and table upload (HIP events)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,7 +209,7 @@ def main():
         "step_ms": [round(x, 4) for x in step_ms],
         "wall_ms_timed_region": round(wall_ms, 2),
         "roofline": {
-            "kernel": "trailing update call Q_s^T C (qt_group_kernel + per-level node_level_kernel + "
+            "kernel": "trailing update call Q_s^T C (leaf_kernel + per-level node_level_kernel + "
                       "scale_rows_kernel; qt_tree_tile_kernel for the next panel's columns)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
@@ -204,44 +256,8 @@ def main():
             del B0, B
         # uneven batch (2000 problems, m log-uniform in [256, 65536], n in {8,16,32,64}),
         # plans from the autotuner; one step = one tsqr_factor_batched call
-        ms, ns = inputs.batched_tsqr_sizes()
-        seed = inputs.SEEDS["batched_tsqr"]
-        P = [inputs.gaussian_device(int(m), int(n), seed * 100003 + i) for i, (m, n) in enumerate(zip(ms, ns))]
-        W = [torch.empty_like(a.t()).t() for a in P]
-        t_tune = time.perf_counter()
-        caqr.tune_batched()
-        t_tune = time.perf_counter() - t_tune
-        times = []
-        for it in range(3 + 10):
-            for w, a in zip(W, P):
-                w.copy_(a)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            Bt = caqr.tsqr_batched(W)
-            e1.record()
-            torch.cuda.synchronize()
-            if it >= 3:
-                times.append(e0.elapsed_time(e1))
-            Bt.close()
-        t = float(np.median(times))
-        alg = float(sum(16.0 * int(m) * int(n) for m, n in zip(ms, ns)))
-        flops = float(sum(2.0 * int(m) * int(n) ** 2 - 2.0 * int(n) ** 3 / 3 for m, n in zip(ms, ns)))
-        plans = {}
-        for m, n in zip(ms, ns):
-            k = "h%d/lpw%d" % caqr.batch_plan_for(int(m), int(n))
-            plans[k] = plans.get(k, 0) + 1
-        sec["batched_tsqr_2000_uneven"] = {
-            "median_ms": round(t, 4), "p10_ms": round(float(np.percentile(times, 10)), 4),
-            "p90_ms": round(float(np.percentile(times, 90)), 4),
-            "matrices_per_s": round(len(ms) / (t * 1e-3), 1), "gflops": round(flops / (t * 1e-3) / 1e9, 1),
-            "algorithmic_GBps": round(alg / (t * 1e-3) / 1e9, 1),
-            "pct_hbm_peak": round(100 * alg / (t * 1e-3) / 1e9 / PEAK_HBM_GBS, 2),
-            "bytes": alg, "tune_s": round(t_tune, 2), "plans": plans,
-            "timed": "one tsqr_factor_batched call incl. planning and table upload (HIP events)"}
-        del P, W
-        torch.cuda.empty_cache()
+        sec["batched_tsqr_2000_uneven"] = batched_line("f64")
+        sec["batched_tsqr_2000_uneven_f32"] = batched_line("f32")
         out["secondary"] = sec
 
     if not args.no_cpu_baseline:

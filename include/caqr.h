@@ -225,7 +225,9 @@ caqr_status_t caqr_trace_read(caqr_handle_t h, caqr_trace_entry_t *out, int64_t 
 /* factors are eliminated along the binary tree, exactly as tsqr_factor does.  */
 /* All problems run in one launch per (leaf height, ceil(n_i/16)) group; the  */
 /* results of problem i are bitwise those of tsqr_factor on it with the same  */
-/* plan (leaf_rows, leaves_per_wg).                                           */
+/* plan (leaf_rows, leaves_per_wg).  CAQR_F32 runs the same steps in single   */
+/* precision (float storage and arithmetic throughout); its results do not    */
+/* depend on the other problems of the batch either.                          */
 /* ------------------------------------------------------------------------ */
 
 typedef enum { CAQR_F64 = 0, CAQR_F32 = 1 } caqr_dtype_t;
@@ -235,12 +237,13 @@ typedef struct caqr_batch_s *caqr_batch_t;
 /* Factor `batch` problems.  m, n, lda: host arrays of length batch; A: host
    array of device pointers, A[i] column-major with leading dimension lda[i].
    On return A[i] holds R_i (top n_i-by-n_i upper triangle, non-negative
-   diagonal) and the reflectors of problem i, as after tsqr_factor.  dt must
-   be CAQR_F64 (CAQR_F32 returns CAQR_ERR_NOT_SUPPORTED).  opts: one plan for
-   every problem, or NULL for the plans measured by caqr_tune_batched (or a
-   fixed size heuristic before any tuning).  Errors: CAQR_ERR_INVALID_VALUE
-   for a negative batch, missing arrays, m_i < 0, lda_i < max(1, m_i), a null
-   A[i] with n_i > 0 or invalid opts; CAQR_ERR_NOT_SUPPORTED for m_i < n_i,
+   diagonal) and the reflectors of problem i, as after tsqr_factor.  dt is the
+   element type of every A[i]: CAQR_F64 (double) or CAQR_F32 (float).  opts:
+   one plan for every problem, or NULL for the plans measured by
+   caqr_tune_batched for dt (or a fixed size heuristic before any tuning).
+   Errors: CAQR_ERR_INVALID_VALUE for a negative batch, missing arrays, an
+   unknown dt, m_i < 0, lda_i < max(1, m_i), a null A[i] with n_i > 0 or
+   invalid opts; CAQR_ERR_NOT_SUPPORTED for m_i < n_i,
    n_i > 64 or m_i > 2^31 - 1; CAQR_ERR_ALLOC; CAQR_ERR_DEVICE.  Arguments are checked before
    anything is enqueued.  Work is enqueued on the handle's stream; *F owns the
    per-problem tau, signs and workspace until caqr_batch_destroy (which waits
@@ -254,16 +257,19 @@ caqr_status_t caqr_batch_destroy(caqr_batch_t F);
 /* The plan used for problem i (leaf_rows, leaves_per_wg). */
 caqr_status_t caqr_batch_get_plan(caqr_batch_t F, int64_t i, caqr_tree_opts_t *plan);
 
-/* Signs D of problem i (n_i doubles, host memory); waits for the factorization. */
+/* Signs D of problem i (n_i doubles, host memory, also for CAQR_F32 batches);
+   waits for the factorization. */
 caqr_status_t caqr_batch_get_signs(caqr_batch_t F, int64_t i, double *d);
 
 /* Autotuner: for n in {8, 16, 32, 64} and m in each power-of-two bucket from
    256 to 65536, times every plan (leaf_rows 64/128/256 x leaves_per_wg 1/2/4)
-   on a batch of synthetic problems filling the device, and keeps the fastest
-   in the handle (launch time only, by HIP events).  Later batched calls with
-   opts == NULL use it: a problem takes the plan of its n bucket (the smallest
-   of 8/16/32/64 that is >= n_i) and of the power-of-two bucket of m_i
-   (clamped to 256 .. 65536).  Synchronous; uses a 128 MiB scratch buffer. */
+   on a batch of synthetic problems of element type dt filling the device, and
+   keeps the fastest in the handle, one table per dt (launch time only, by HIP
+   events).  Later batched calls of that dt with opts == NULL use it: a
+   problem takes the plan of its n bucket (the smallest of 8/16/32/64 that is
+   >= n_i) and of the power-of-two bucket of m_i (clamped to 256 .. 65536).
+   Synchronous; uses a scratch buffer of 2^24 elements of dt (128 MiB for
+   CAQR_F64).  Errors: CAQR_ERR_INVALID_VALUE for an unknown dt. */
 caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt);
 
 /* The plan a batched call with opts == NULL would use for an m-by-n problem. */

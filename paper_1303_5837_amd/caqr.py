@@ -196,19 +196,19 @@ def handle(device: int = 0) -> Handle:
     return h
 
 
-def fortran(x, device="cuda") -> torch.Tensor:
-    """Copy a 2-D array into a column-major float64 CUDA tensor."""
-    t = torch.as_tensor(x, dtype=torch.float64)
+def fortran(x, device="cuda", dtype=torch.float64) -> torch.Tensor:
+    """Copy a 2-D array into a column-major CUDA tensor (float64 by default)."""
+    t = torch.as_tensor(x, dtype=dtype)
     if t.ndim == 1:
         t = t[:, None]
-    out = torch.empty((t.shape[1], t.shape[0]), dtype=torch.float64, device=device).t()
+    out = torch.empty((t.shape[1], t.shape[0]), dtype=dtype, device=device).t()
     out.copy_(t)
     return out
 
 
-def _ld(t: torch.Tensor) -> int:
-    if t.dtype != torch.float64 or not t.is_cuda or t.ndim != 2:
-        raise ValueError("expected a 2-D float64 CUDA tensor")
+def _ld(t: torch.Tensor, dtypes=(torch.float64,)) -> int:
+    if t.dtype not in dtypes or not t.is_cuda or t.ndim != 2:
+        raise ValueError("expected a 2-D " + "/".join(str(d).split(".")[-1] for d in dtypes) + " CUDA tensor")
     m, n = t.shape
     if t.stride(0) != 1 and not (n <= 1 and t.is_contiguous()):
         raise ValueError("matrix must be column-major (stride (1, ld))")
@@ -338,30 +338,42 @@ class Batch:
             pass
 
 
+_DT = {torch.float64: F64, torch.float32: F32}
+
+
+def _dtype_code(dtype) -> int:
+    if dtype not in _DT:
+        raise ValueError("dtype must be torch.float64 or torch.float32")
+    return _DT[dtype]
+
+
 def tsqr_batched(As, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0) -> Batch:
-    """In place TSQR of every column-major CUDA tensor in ``As`` (one plan for all
-    when leaf_rows/leaves_per_wg are given, else the tuned or default plans)."""
+    """In place TSQR of every column-major CUDA tensor in ``As`` (all float64 or
+    all float32; one plan for all when leaf_rows/leaves_per_wg are given, else
+    the tuned or default plans of that type)."""
     h = handle(device)
     k = len(As)
+    dtype = As[0].dtype if k else torch.float64
+    dt = _dtype_code(dtype)
     m = (ctypes.c_int64 * max(1, k))(*[int(a.shape[0]) for a in As])
     n = (ctypes.c_int64 * max(1, k))(*[int(a.shape[1]) for a in As])
-    ld = (ctypes.c_int64 * max(1, k))(*[_ld(a) for a in As])
+    ld = (ctypes.c_int64 * max(1, k))(*[_ld(a, (dtype,)) for a in As])
     ptrs = (ctypes.c_void_p * max(1, k))(*[a.data_ptr() for a in As])
     b = ctypes.c_void_p()
-    _check(_lib().tsqr_factor_batched(h.ptr, k, m, n, ptrs, ld, F64, _opts(leaf_rows, leaves_per_wg),
+    _check(_lib().tsqr_factor_batched(h.ptr, k, m, n, ptrs, ld, dt, _opts(leaf_rows, leaves_per_wg),
                                       ctypes.byref(b)), "tsqr_factor_batched")
     return Batch(h, b, As)
 
 
-def tune_batched(device: int = 0):
-    """Measure the batched plans per size bucket (stored in the handle)."""
+def tune_batched(device: int = 0, dtype=torch.float64):
+    """Measure the batched plans of one element type per size bucket (stored in the handle)."""
     h = handle(device)
-    _check(_lib().caqr_tune_batched(h.ptr, F64), "caqr_tune_batched")
+    _check(_lib().caqr_tune_batched(h.ptr, _dtype_code(dtype)), "caqr_tune_batched")
 
 
-def batch_plan_for(m: int, n: int, device: int = 0):
+def batch_plan_for(m: int, n: int, device: int = 0, dtype=torch.float64):
     """(leaf_rows, leaves_per_wg) a batched call without a plan uses for an m-by-n problem."""
     h = handle(device)
     o = TreeOpts()
-    _check(_lib().caqr_batch_plan_for(h.ptr, m, n, F64, ctypes.byref(o)), "caqr_batch_plan_for")
+    _check(_lib().caqr_batch_plan_for(h.ptr, m, n, _dtype_code(dtype), ctypes.byref(o)), "caqr_batch_plan_for")
     return int(o.leaf_rows), int(o.leaves_per_wg)

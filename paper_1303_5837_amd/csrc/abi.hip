@@ -67,28 +67,31 @@ struct caqr_handle_s {
   std::vector<hipEvent_t> event_pool; // free events
   hipStream_t side = nullptr;         // look-ahead stream (default priority, created on first use)
   hipEvent_t sync_ev[2] = {nullptr, nullptr};  // ordering events between the two streams
-  // batched-TSQR plans measured by caqr_tune_batched: [n bucket 8/16/32/64][log2 m - 8]
-  bool tuned = false;
-  caqr_tree_opts_t tuned_plan[4][9] = {};
+  // batched-TSQR plans measured by caqr_tune_batched, per element type
+  // (CAQR_F64, CAQR_F32): [n bucket 8/16/32/64][log2 m - 8]
+  bool tuned[2] = {false, false};
+  caqr_tree_opts_t tuned_plan[2][4][9] = {};
 };
 
 struct caqr_batch_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  caqr_dtype_t dt = CAQR_F64;
   int64_t count = 0;
   std::vector<int64_t> m, n;
   std::vector<caqr_tree_opts_t> plan;
-  std::vector<int64_t> d_off;           // offset (doubles) of D_i in `small`, -1 for n_i = 0
-  std::vector<caqr::PanelParams> probs; // grouped by (leaf rows, nq)
+  std::vector<int64_t> d_off;           // offset (elements) of D_i in `small`, -1 for n_i = 0
+  std::vector<caqr::PanelParams> probs; // grouped by (leaf rows, nq); for F32, converted to
+  std::vector<caqr::PanelParams32> probs32;  // probs32 before the upload
   std::vector<int2> items;              // (problem within its group, first leaf) per workgroup
   struct Group {
     int leaf_rows, nq;
     int64_t prob0, nprob, item0, nitem, rows, leaves;
   };
   std::vector<Group> groups;
-  double *small = nullptr;              // tau_leaf, tau_node, d of every problem
+  void *small = nullptr;                // tau_leaf, tau_node, d of every problem (batch's type)
   unsigned *tickets = nullptr;          // one counter per leaf of every problem
-  caqr::PanelParams *probs_dev = nullptr;
+  void *probs_dev = nullptr;            // PanelParams or PanelParams32 table
   int2 *items_dev = nullptr;
 };
 
@@ -453,13 +456,16 @@ caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, dou
 
 // ---- batched TSQR
 
-__global__ void fill_pattern_kernel(double *p, size_t n) {
+template <class T>
+__global__ void fill_pattern_kernel(T *p, size_t n) {
   // deterministic, nonzero, well-scaled values (tuning input only)
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const unsigned x = (unsigned)(i * 2654435761u) >> 8;
-    p[i] = (double)(x & 0xFFFF) / 32768.0 - 1.0 + 1.0 / 4096.0;
+    p[i] = (T)((double)(x & 0xFFFF) / 32768.0 - 1.0 + 1.0 / 4096.0);
   }
 }
+
+size_t elem_size(caqr_dtype_t dt) { return dt == CAQR_F32 ? sizeof(float) : sizeof(double); }
 
 int n_bucket(int64_t n) { return n <= 8 ? 0 : n <= 16 ? 1 : n <= 32 ? 2 : 3; }
 
@@ -471,8 +477,8 @@ int m_bucket(int64_t m) {
 
 // Plan of one problem when the caller gives none: the tuned table, else leaf
 // height by size and as many leaves per workgroup as keep four or more of them.
-caqr_tree_opts_t default_plan(caqr_handle_t h, int64_t m, int64_t n) {
-  if (h->tuned) return h->tuned_plan[n_bucket(n)][m_bucket(m)];
+caqr_tree_opts_t default_plan(caqr_handle_t h, int64_t m, int64_t n, caqr_dtype_t dt) {
+  if (h->tuned[dt]) return h->tuned_plan[dt][n_bucket(n)][m_bucket(m)];
   caqr_tree_opts_t o{};
   o.leaf_rows = m >= 1024 ? 256 : (m >= 256 ? 128 : 64);
   const int64_t L = (m + o.leaf_rows - 1) / o.leaf_rows;
@@ -486,7 +492,7 @@ caqr_status_t check_batch_args(caqr_handle_t h, int64_t batch, const int64_t *m,
   if (batch > 0 && (!m || !n || !A || !lda)) return CAQR_ERR_INVALID_VALUE;
   if (dt != CAQR_F64 && dt != CAQR_F32) return CAQR_ERR_INVALID_VALUE;
   if (check_opts(opts)) return CAQR_ERR_INVALID_VALUE;
-  bool unsupported = dt != CAQR_F64;
+  bool unsupported = false;
   for (int64_t i = 0; i < batch; ++i) {
     if (m[i] < 0 || n[i] < 0 || lda[i] < std::max<int64_t>(1, m[i])) return CAQR_ERR_INVALID_VALUE;
     if (n[i] > 0 && !A[i]) return CAQR_ERR_INVALID_VALUE;
@@ -500,29 +506,30 @@ caqr_status_t check_batch_args(caqr_handle_t h, int64_t batch, const int64_t *m,
 // Plan every problem, allocate the batch's buffers and upload its tables
 // (nothing is launched).
 caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, const int64_t *n, void *const *A,
-                            const int64_t *lda, const caqr_tree_opts_t *opts, caqr_batch_t *out) {
+                            const int64_t *lda, caqr_dtype_t dt, const caqr_tree_opts_t *opts, caqr_batch_t *out) {
   caqr_batch_s *B = new (std::nothrow) caqr_batch_s;
   if (!B) return CAQR_ERR_ALLOC;
   B->device = h->device;
   B->stream = h->stream;
+  B->dt = dt;
   B->count = batch;
   B->m.assign(m, m + batch);
   B->n.assign(n, n + batch);
   B->plan.resize(batch);
   B->d_off.assign(batch, -1);
   std::vector<int64_t> L(batch, 0), tau_off(batch, 0), tick_off(batch, 0);
-  int64_t small_doubles = 0, ticket_count = 0;
+  int64_t small_elems = 0, ticket_count = 0;
   for (int64_t i = 0; i < batch; ++i) {
-    caqr_tree_opts_t o = opts ? *opts : default_plan(h, m[i], n[i]);
+    caqr_tree_opts_t o = opts ? *opts : default_plan(h, m[i], n[i], dt);
     if (!o.leaf_rows) o.leaf_rows = 256;
     if (!o.leaves_per_wg) o.leaves_per_wg = 4;
     B->plan[i] = o;
     if (n[i] == 0) continue;
     L[i] = (m[i] + o.leaf_rows - 1) / o.leaf_rows;
-    tau_off[i] = small_doubles;
-    small_doubles += 2 * L[i] * kNbMax;
-    B->d_off[i] = small_doubles;
-    small_doubles += kNbMax;
+    tau_off[i] = small_elems;
+    small_elems += 2 * L[i] * kNbMax;
+    B->d_off[i] = small_elems;
+    small_elems += kNbMax;
     tick_off[i] = ticket_count;
     ticket_count += L[i];
   }
@@ -533,7 +540,7 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
       caqr_batch_s::Group g{kLeaf[hi], nq, (int64_t)B->probs.size(), 0, (int64_t)B->items.size(), 0, 0, 0};
       for (int64_t i = 0; i < batch; ++i) {
         if (n[i] == 0 || B->plan[i].leaf_rows != kLeaf[hi] || (n[i] + 15) / 16 != nq) continue;
-        caqr::PanelParams p{};
+        caqr::PanelParams p{};  // pointers hold offsets until the buffers exist
         p.A = static_cast<double *>(A[i]);
         p.lda = lda[i];
         p.m = m[i];
@@ -554,34 +561,56 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
       g.nitem = (int64_t)B->items.size() - g.item0;
       if (g.nprob) B->groups.push_back(g);
     }
-  const size_t bytes = small_doubles * sizeof(double) + ticket_count * sizeof(unsigned) +
-                       B->probs.size() * sizeof(caqr::PanelParams) + B->items.size() * sizeof(int2);
+  const size_t es = elem_size(dt);
+  const size_t table_bytes = B->probs.size() * (dt == CAQR_F32 ? sizeof(caqr::PanelParams32) : sizeof(caqr::PanelParams));
+  const size_t bytes = small_elems * es + ticket_count * sizeof(unsigned) + table_bytes + B->items.size() * sizeof(int2);
   if (h->ws_limit && bytes > h->ws_limit) {
     delete B;
     return CAQR_ERR_ALLOC;
   }
   bool ok = true;
-  if (small_doubles) ok = ok && hipMalloc(&B->small, small_doubles * sizeof(double)) == hipSuccess;
+  if (small_elems) ok = ok && hipMalloc(&B->small, small_elems * es) == hipSuccess;
   if (ticket_count) ok = ok && hipMalloc(&B->tickets, ticket_count * sizeof(unsigned)) == hipSuccess;
-  if (!B->probs.empty()) ok = ok && hipMalloc(&B->probs_dev, B->probs.size() * sizeof(caqr::PanelParams)) == hipSuccess;
+  if (table_bytes) ok = ok && hipMalloc(&B->probs_dev, table_bytes) == hipSuccess;
   if (!B->items.empty()) ok = ok && hipMalloc(&B->items_dev, B->items.size() * sizeof(int2)) == hipSuccess;
   if (!ok) {
     caqr_batch_destroy(B);
     return CAQR_ERR_ALLOC;
   }
-  for (auto &p : B->probs) {
-    p.tau_leaf = B->small + reinterpret_cast<intptr_t>(p.tau_leaf);
-    p.tau_node = B->small + reinterpret_cast<intptr_t>(p.tau_node);
-    p.d = B->small + reinterpret_cast<intptr_t>(p.d);
-    p.tickets = B->tickets + reinterpret_cast<intptr_t>(p.tickets);
+  if (dt == CAQR_F32) {
+    float *small = static_cast<float *>(B->small);
+    B->probs32.reserve(B->probs.size());
+    for (const auto &p : B->probs) {
+      caqr::PanelParams32 q{};
+      q.A = reinterpret_cast<float *>(p.A);
+      q.lda = p.lda;
+      q.m = p.m;
+      q.b = p.b;
+      q.L = p.L;
+      q.lpw = p.lpw;
+      q.tau_leaf = small + reinterpret_cast<intptr_t>(p.tau_leaf);
+      q.tau_node = small + reinterpret_cast<intptr_t>(p.tau_node);
+      q.d = small + reinterpret_cast<intptr_t>(p.d);
+      q.tickets = B->tickets + reinterpret_cast<intptr_t>(p.tickets);
+      B->probs32.push_back(q);
+    }
+    B->probs.clear();
+  } else {
+    double *small = static_cast<double *>(B->small);
+    for (auto &p : B->probs) {
+      p.tau_leaf = small + reinterpret_cast<intptr_t>(p.tau_leaf);
+      p.tau_node = small + reinterpret_cast<intptr_t>(p.tau_node);
+      p.d = small + reinterpret_cast<intptr_t>(p.d);
+      p.tickets = B->tickets + reinterpret_cast<intptr_t>(p.tickets);
+    }
   }
   if (ticket_count) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, h->stream, B->tickets, (size_t)ticket_count);
     ok = hipGetLastError() == hipSuccess;
   }
-  if (ok && !B->probs.empty())
-    ok = hipMemcpyAsync(B->probs_dev, B->probs.data(), B->probs.size() * sizeof(caqr::PanelParams),
-                        hipMemcpyHostToDevice, h->stream) == hipSuccess;
+  if (ok && table_bytes)
+    ok = hipMemcpyAsync(B->probs_dev, dt == CAQR_F32 ? (const void *)B->probs32.data() : (const void *)B->probs.data(),
+                        table_bytes, hipMemcpyHostToDevice, h->stream) == hipSuccess;
   if (ok && !B->items.empty())
     ok = hipMemcpyAsync(B->items_dev, B->items.data(), B->items.size() * sizeof(int2), hipMemcpyHostToDevice,
                         h->stream) == hipSuccess;
@@ -598,9 +627,13 @@ caqr_status_t batch_launch(caqr_handle_t h, caqr_batch_t B) {
   for (size_t gi = 0; gi < B->groups.size(); ++gi) {
     const auto &g = B->groups[gi];
     TraceScope ts(h, CAQR_TRACE_PANEL, (int)gi, g.rows, 16 * g.nq, g.leaf_rows, (int)std::min<int64_t>(g.leaves, INT32_MAX));
-    if (launch_tsqr_panel_batched(B->probs_dev + g.prob0, B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq,
-                                  h->stream) != hipSuccess)
-      return CAQR_ERR_DEVICE;
+    const hipError_t e =
+        B->dt == CAQR_F32
+            ? launch_tsqr_panel_batched(static_cast<const caqr::PanelParams32 *>(B->probs_dev) + g.prob0,
+                                        B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, h->stream)
+            : launch_tsqr_panel_batched(static_cast<const caqr::PanelParams *>(B->probs_dev) + g.prob0,
+                                        B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, h->stream);
+    if (e != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return CAQR_SUCCESS;
 }
@@ -842,7 +875,7 @@ caqr_status_t tsqr_factor_batched(caqr_handle_t h, int64_t batch, const int64_t 
   if (st) return st;
   DeviceGuard g(h->device);
   caqr_batch_t B = nullptr;
-  if ((st = batch_prepare(h, batch, m, n, A, lda, opts, &B))) return st;
+  if ((st = batch_prepare(h, batch, m, n, A, lda, dt, opts, &B))) return st;
   if ((st = batch_launch(h, B))) {
     caqr_batch_destroy(B);
     return st;
@@ -874,27 +907,36 @@ caqr_status_t caqr_batch_get_signs(caqr_batch_t F, int64_t i, double *d) {
   if (F->n[i] == 0) return CAQR_SUCCESS;
   DeviceGuard g(F->device);
   if (hipStreamSynchronize(F->stream) != hipSuccess) return CAQR_ERR_DEVICE;
-  if (hipMemcpy(d, F->small + F->d_off[i], F->n[i] * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+  if (F->dt == CAQR_F32) {
+    std::vector<float> tmp(F->n[i]);
+    if (hipMemcpy(tmp.data(), static_cast<const float *>(F->small) + F->d_off[i], F->n[i] * sizeof(float),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return CAQR_ERR_DEVICE;
+    for (int64_t j = 0; j < F->n[i]; ++j) d[j] = tmp[j];
+  } else if (hipMemcpy(d, static_cast<const double *>(F->small) + F->d_off[i], F->n[i] * sizeof(double),
+                       hipMemcpyDeviceToHost) != hipSuccess) {
     return CAQR_ERR_DEVICE;
+  }
   return CAQR_SUCCESS;
 }
 
 caqr_status_t caqr_batch_plan_for(caqr_handle_t h, int64_t m, int64_t n, caqr_dtype_t dt, caqr_tree_opts_t *plan) {
   if (!h || !plan || m < 0 || n < 0) return CAQR_ERR_INVALID_VALUE;
-  if (dt != CAQR_F64) return dt == CAQR_F32 ? CAQR_ERR_NOT_SUPPORTED : CAQR_ERR_INVALID_VALUE;
-  *plan = default_plan(h, m, n);
+  if (dt != CAQR_F64 && dt != CAQR_F32) return CAQR_ERR_INVALID_VALUE;
+  *plan = default_plan(h, m, n, dt);
   return CAQR_SUCCESS;
 }
 
 caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
   if (!h) return CAQR_ERR_INVALID_VALUE;
-  if (dt != CAQR_F64) return dt == CAQR_F32 ? CAQR_ERR_NOT_SUPPORTED : CAQR_ERR_INVALID_VALUE;
+  if (dt != CAQR_F64 && dt != CAQR_F32) return CAQR_ERR_INVALID_VALUE;
   DeviceGuard g(h->device);
   constexpr int64_t kRows = (int64_t)1 << 18;  // rows of every tuning batch (x 64 columns max)
   const size_t elems = (size_t)kRows * kNbMax;
-  if (h->ws_limit && elems * sizeof(double) > h->ws_limit) return CAQR_ERR_ALLOC;
-  double *scratch = nullptr;
-  if (hipMalloc(&scratch, elems * sizeof(double)) != hipSuccess) return CAQR_ERR_ALLOC;
+  const size_t es = elem_size(dt);
+  if (h->ws_limit && elems * es > h->ws_limit) return CAQR_ERR_ALLOC;
+  char *scratch = nullptr;
+  if (hipMalloc(&scratch, elems * es) != hipSuccess) return CAQR_ERR_ALLOC;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   caqr_status_t st = CAQR_SUCCESS;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = CAQR_ERR_DEVICE;
@@ -911,7 +953,7 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
       const int64_t K = std::max<int64_t>(1, kRows / mm);
       std::vector<int64_t> mv(K, mm), nv(K, nn), lv(K, mm);
       std::vector<void *> av(K);
-      for (int64_t i = 0; i < K; ++i) av[i] = scratch + i * mm * nn;
+      for (int64_t i = 0; i < K; ++i) av[i] = scratch + (size_t)(i * mm * nn) * es;
       float best = 0.f;
       for (int hi = 0; hi < 3 && !st; ++hi)
         for (int li = 0; li < 3 && !st; ++li) {
@@ -919,10 +961,15 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
           o.leaf_rows = kLeaf[hi];
           o.leaves_per_wg = kLpw[li];
           caqr_batch_t B = nullptr;
-          if ((st = batch_prepare(h, K, mv.data(), nv.data(), av.data(), lv.data(), &o, &B))) break;
+          if ((st = batch_prepare(h, K, mv.data(), nv.data(), av.data(), lv.data(), dt, &o, &B))) break;
           float ts[5];
           for (int rep = 0; rep < 5 && !st; ++rep) {
-            hipLaunchKernelGGL(fill_pattern_kernel, dim3(1024), dim3(256), 0, h->stream, scratch, (size_t)(K * mm * nn));
+            if (dt == CAQR_F32)
+              hipLaunchKernelGGL(fill_pattern_kernel<float>, dim3(1024), dim3(256), 0, h->stream,
+                                 reinterpret_cast<float *>(scratch), (size_t)(K * mm * nn));
+            else
+              hipLaunchKernelGGL(fill_pattern_kernel<double>, dim3(1024), dim3(256), 0, h->stream,
+                                 reinterpret_cast<double *>(scratch), (size_t)(K * mm * nn));
             if (hipEventRecord(e0, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
             if (!st) st = batch_launch(h, B);
             if (!st && hipEventRecord(e1, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
@@ -944,8 +991,8 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(scratch);
   if (st) return st;
-  std::memcpy(h->tuned_plan, table, sizeof(table));
-  h->tuned = true;
+  std::memcpy(h->tuned_plan[dt], table, sizeof(table));
+  h->tuned[dt] = true;
   return CAQR_SUCCESS;
 }
 

@@ -36,14 +36,24 @@ __device__ __forceinline__ double dpp_f64(double x) {
   return __hiloint2double(hi, lo);
 }
 
-// 1/x from the hardware estimate refined by two Newton steps (within about
-// one ulp; used only where x is a normal number well inside the range).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// 1/x from the hardware estimate refined by Newton steps (within about one
+// ulp; used only where x is a normal number well inside the range).
 __device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(r, e, r);
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = fmaf(-x, r, 1.0f);
+  return fmaf(r, e, r);
 }
 
 // Sum over the 16 lanes of a DPP row.  Every lane of the row ends with the
@@ -65,11 +75,31 @@ __device__ __forceinline__ double row16_max(double x) {
   return x;
 }
 
+__device__ __forceinline__ float row16_sum(float x) {
+  x += dpp_f32<kDppQuadXor1>(x);
+  x += dpp_f32<kDppQuadXor2>(x);
+  x += dpp_f32<kDppRowHalfMirror>(x);
+  x += dpp_f32<kDppRowMirror>(x);
+  return x;
+}
+
+__device__ __forceinline__ float row16_max(float x) {
+  x = fmaxf(x, dpp_f32<kDppQuadXor1>(x));
+  x = fmaxf(x, dpp_f32<kDppQuadXor2>(x));
+  x = fmaxf(x, dpp_f32<kDppRowHalfMirror>(x));
+  x = fmaxf(x, dpp_f32<kDppRowMirror>(x));
+  return x;
+}
+
 // Value of x in lane `lane` (wave-uniform) broadcast to the whole wave.
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
   int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
   return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_t(double x, int lane) { return readlane_f64(x, lane); }
+__device__ __forceinline__ float readlane_t(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
 // Agent-scope release/acquire around the last-arriver tickets of the device

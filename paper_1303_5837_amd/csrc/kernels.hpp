@@ -12,19 +12,23 @@ constexpr int kUpdTile = 32;
 // tickets, L per tile); wider ones run one launch per tree level.
 constexpr int kTreeTiles = 4;
 
-// One panel of the factorization: rows [0, m) x columns [0, b) at A (lda).
-struct PanelParams {
-  double *A;
+// One panel of the factorization: rows [0, m) x columns [0, b) at A (lda),
+// elements of type T (double, or float for the single-precision batched TSQR).
+template <class T>
+struct PanelParamsT {
+  T *A;
   int64_t lda;
   int64_t m;
   int b;          // panel width, 1..64
   int L;          // number of leaves (row blocks of leaf_rows rows)
   int lpw;        // leaves per workgroup (1, 2, 4)
-  double *tau_leaf;   // [L][64]
-  double *tau_node;   // [L][64], node id = eliminated leaf (1..L-1)
-  double *d;          // [64] signs of the root R
+  T *tau_leaf;    // [L][64]
+  T *tau_node;    // [L][64], node id = eliminated leaf (1..L-1)
+  T *d;           // [64] signs of the root R
   unsigned *tickets;  // [L], zero on entry and on exit
 };
+using PanelParams = PanelParamsT<double>;
+using PanelParams32 = PanelParamsT<float>;
 
 // Application of one panel's Q (or Q^T) to C (m rows x k columns at C, ldc).
 // Leaves, nodes and their reflectors as produced by the panel kernel.
@@ -54,6 +58,8 @@ hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s)
 // probs (device) holds one PanelParams per problem, items (device) one
 // (problem, first leaf) pair per workgroup.
 hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items, int nitems, int leaf_rows, int nq,
+                                     hipStream_t s);
+hipError_t launch_tsqr_panel_batched(const PanelParams32 *probs, const int2 *items, int nitems, int leaf_rows, int nq,
                                      hipStream_t s);
 
 // C <- Q^T C for one panel: leaf updates and the tree bottom-up, then rows

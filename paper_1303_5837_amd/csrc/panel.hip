@@ -37,12 +37,22 @@ namespace caqr {
 
 namespace {
 
+template <class T>
 struct PanelSmem {
-  double v[2][16 * 16];  // Householder vector of the current step (by row), double-buffered
-  double tau[2];
-  double taus[kMaxB];
-  double dsign[kMaxB];
+  T v[2][16 * 16];  // Householder vector of the current step (by row), double-buffered
+  T tau[2];
+  T taus[kMaxB];
+  T dsign[kMaxB];
   int flag;
+};
+
+// Range of the normal numbers of T.
+template <class T> struct Lim;
+template <> struct Lim<double> {
+  static constexpr double tiny = DBL_MIN, huge = DBL_MAX;
+};
+template <> struct Lim<float> {
+  static constexpr float tiny = FLT_MIN, huge = FLT_MAX;
 };
 
 // One Householder step per column j = 0..b-1 on the block held in a[][]:
@@ -52,8 +62,9 @@ struct PanelSmem {
 // tau = (beta - alpha) / beta, v = [1; x(2:) / (alpha - beta)]; x(2:) == 0 gives
 // tau = 0 (H = I).  The norm is an unscaled sum of squares, recomputed with
 // power-of-two scaling when alpha^2 + sigma is zero, subnormal or overflows.
-template <int NCH, int NQ, int NACT, bool STACK>
-__device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, PanelSmem &sm) {
+// T is double, or float for the single-precision batched TSQR (same steps).
+template <class T, int NCH, int NQ, int NACT, bool STACK>
+__device__ __forceinline__ void householder_steps(T (&a)[NCH][NQ], int b, PanelSmem<T> &sm) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int r = lane & 15;
@@ -67,28 +78,28 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
       if (c == cj) {
         // ---- owner DPP row: reflector of column j (slot Q of this thread)
         // sum of squares below the diagonal: four partial sums (short chain)
-        double sp[4] = {0.0, 0.0, 0.0, 0.0};
+        T sp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int i = 0; i < NACT; ++i) {
           const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
           if (!act) continue;
           const bool below = (i > Q) || (r > cj);
-          const double e = a[i][Q];
+          const T e = a[i][Q];
           sp[i & 3] = below ? fma(e, e, sp[i & 3]) : sp[i & 3];
         }
-        double sig = row16_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
-        const double alpha = readlane_f64(a[Q][Q], (cj & 3) * 16 + cj);
-        const double s2 = fma(alpha, alpha, sig);
+        T sig = row16_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
+        const T alpha = readlane_t(a[Q][Q], (cj & 3) * 16 + cj);
+        const T s2 = fma(alpha, alpha, sig);
         // The reflector is formed from x scaled by 2^sh: sh = 0 normally; when
         // alpha^2 + sigma is zero, subnormal, overflowing or NaN, sh = -ilogb(max|x|)
         // (ldexp per element is exact), so that mu, tau and 1 / (alpha - beta)
         // are computed on normal numbers.
         int sh = 0;
-        double alpha_s = alpha, sig_s = sig, mu_s;
-        if (s2 >= DBL_MIN && s2 <= DBL_MAX) {
+        T alpha_s = alpha, sig_s = sig, mu_s;
+        if (s2 >= Lim<T>::tiny && s2 <= Lim<T>::huge) {
           mu_s = sqrt(s2);
         } else {
-          double mx = 0.0;
+          T mx = T(0);
 #pragma unroll
           for (int i = 0; i < NACT; ++i) {
             const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
@@ -97,32 +108,34 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
             mx = inx ? fmax(mx, fabs(a[i][Q])) : mx;
           }
           mx = row16_max(mx);
-          if (mx == 0.0 || !(mx <= DBL_MAX)) {  // zero column, or Inf/NaN (propagated)
-            mu_s = (mx == 0.0) ? 0.0 : sqrt(s2);
-            sig_s = (mx == 0.0) ? 0.0 : sig;
+          if (mx == T(0) || !(mx <= Lim<T>::huge)) {  // zero column, or Inf/NaN (propagated)
+            mu_s = (mx == T(0)) ? T(0) : sqrt(s2);
+            sig_s = (mx == T(0)) ? T(0) : sig;
           } else {
             sh = -ilogb(mx);
-            double ss = 0.0;
+            // the same summation order as the unscaled sum above, so that
+            // R(2^k A) = 2^k R(A) holds bitwise on this path too
+            T ss[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int i = 0; i < NACT; ++i) {
               const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
               if (!act) continue;
               const bool below = (i > Q) || (r > cj);
-              const double e = ldexp(a[i][Q], sh);
-              ss = below ? fma(e, e, ss) : ss;
+              const T e = ldexp(a[i][Q], sh);
+              ss[i & 3] = below ? fma(e, e, ss[i & 3]) : ss[i & 3];
             }
-            sig_s = row16_sum(ss);
+            sig_s = row16_sum((ss[0] + ss[1]) + (ss[2] + ss[3]));
             alpha_s = ldexp(alpha, sh);
             mu_s = sqrt(fma(alpha_s, alpha_s, sig_s));
           }
         }
-        double beta, tau, scal;
-        if (sig_s == 0.0) {
+        T beta, tau, scal;
+        if (sig_s == T(0)) {
           beta = alpha;
-          tau = 0.0;
-          scal = 0.0;
+          tau = T(0);
+          scal = T(0);
         } else {
-          const double beta_s = -copysign(mu_s, alpha_s);
+          const T beta_s = -copysign(mu_s, alpha_s);
           tau = (beta_s - alpha_s) / beta_s;
           // |alpha - beta| = |alpha| + mu lies in [mu, 2 mu], a normal number:
           // its reciprocal from the hardware estimate refined by two Newton
@@ -134,15 +147,15 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
         for (int i = 0; i < NACT; ++i) {
           const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
           if (!act) continue;
-          double vv;
+          T vv;
           if (i > Q || r > cj) {
             vv = (sh == 0 ? a[i][Q] : ldexp(a[i][Q], sh)) * scal;
             a[i][Q] = vv;
           } else if (r == cj && i == Q) {
-            vv = 1.0;
+            vv = T(1);
             a[i][Q] = beta;
           } else {
-            vv = 0.0;
+            vv = T(0);
           }
           sm.v[par][16 * i + r] = vv;
         }
@@ -155,35 +168,35 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
       // ---- every thread: w = v^T A(:, col) for its column slots, then the rank-1 update.
       // v is read from LDS where it is used (not held across the reductions).
       // Slots whose columns are all finished (q < Q) are skipped.
-      const double tau = sm.tau[par];
-      const double *vrow = sm.v[par] + r;
-      double p[2][NQ];  // two partial sums per slot (half the dependency chain)
+      const T tau = sm.tau[par];
+      const T *vrow = sm.v[par] + r;
+      T p[2][NQ];  // two partial sums per slot (half the dependency chain)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) p[0][q] = p[1][q] = 0.0;
+      for (int q = 0; q < NQ; ++q) p[0][q] = p[1][q] = T(0);
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
         const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
         if (!act) continue;
-        const double vi = vrow[16 * i];
+        const T vi = vrow[16 * i];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (q < Q) continue;
           p[i & 1][q] = fma(vi, a[i][q], p[i & 1][q]);
         }
       }
-      double coef[NQ];
+      T coef[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (q < Q) continue;
-        const double w = row16_sum(p[0][q] + p[1][q]);
+        const T w = row16_sum(p[0][q] + p[1][q]);
         const int col = c + 16 * q;
-        coef[q] = (col > j && col < b) ? tau * w : 0.0;
+        coef[q] = (col > j && col < b) ? tau * w : T(0);
       }
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
         const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
         if (!act) continue;
-        const double vi = vrow[16 * i];
+        const T vi = vrow[16 * i];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (q < Q) continue;  // finished columns are never updated
@@ -195,14 +208,15 @@ __device__ __forceinline__ void householder_steps(double (&a)[NCH][NQ], int b, P
 }
 
 // Global element (row, col) of the panel, row within [0, m).
-__device__ __forceinline__ double *pan(const PanelParams &p, int64_t row, int col) {
+template <class T>
+__device__ __forceinline__ T *pan(const PanelParamsT<T> &p, int64_t row, int col) {
   return p.A + row + (int64_t)col * p.lda;
 }
 
 // Load the upper triangle of the R stored at slot `leaf` into chunks
 // base..base+NQ-1 (zeros elsewhere).
-template <int NCH, int NQ>
-__device__ __forceinline__ void load_r(double (&a)[NCH][NQ], const PanelParams &p, int64_t slot_row, int base) {
+template <class T, int NCH, int NQ>
+__device__ __forceinline__ void load_r(T (&a)[NCH][NQ], const PanelParamsT<T> &p, int64_t slot_row, int base) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
   const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
@@ -212,14 +226,14 @@ __device__ __forceinline__ void load_r(double (&a)[NCH][NQ], const PanelParams &
     for (int q = 0; q < NQ; ++q) {
       const int row = 16 * i + r, col = c + 16 * q;
       const int64_t grow = slot_row + row;
-      a[base + i][q] = (row <= col && col < p.b && grow < p.m) ? *pan(p, grow, col) : 0.0;
+      a[base + i][q] = (row <= col && col < p.b && grow < p.m) ? *pan(p, grow, col) : T(0);
     }
 }
 
 // Store the upper triangle (incl. diagonal) held in chunks base..base+NQ-1 to
 // the rows starting at slot_row.
-template <int NCH, int NQ>
-__device__ __forceinline__ void store_upper(const double (&a)[NCH][NQ], const PanelParams &p, int64_t slot_row,
+template <class T, int NCH, int NQ>
+__device__ __forceinline__ void store_upper(const T (&a)[NCH][NQ], const PanelParamsT<T> &p, int64_t slot_row,
                                             int base) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
@@ -237,25 +251,26 @@ __device__ __forceinline__ void store_upper(const double (&a)[NCH][NQ], const Pa
 // Eliminate the R at slot `right` against the R at slot `left` (both read from
 // global).  Writes V over the right slot, tau/T of node `right`, and the new
 // R over the left slot.  The new R stays in chunks 0..NQ-1.
-template <int NCH, int NQ>
-__device__ __forceinline__ void combine(double (&a)[NCH][NQ], const PanelParams &p, int left, int right, int h,
-                                        PanelSmem &sm) {
+template <class T, int NCH, int NQ>
+__device__ __forceinline__ void combine(T (&a)[NCH][NQ], const PanelParamsT<T> &p, int left, int right, int h,
+                                        PanelSmem<T> &sm) {
   const int64_t lrow = (int64_t)left * h, rrow = (int64_t)right * h;
-  load_r<NCH, NQ>(a, p, lrow, 0);
-  load_r<NCH, NQ>(a, p, rrow, NQ);
+  load_r<T, NCH, NQ>(a, p, lrow, 0);
+  load_r<T, NCH, NQ>(a, p, rrow, NQ);
   __syncthreads();
-  householder_steps<NCH, NQ, 2 * NQ, true>(a, p.b, sm);
-  store_upper<NCH, NQ>(a, p, rrow, NQ);  // V of the node
-  store_upper<NCH, NQ>(a, p, lrow, 0);   // R of the survivor
+  householder_steps<T, NCH, NQ, 2 * NQ, true>(a, p.b, sm);
+  store_upper<T, NCH, NQ>(a, p, rrow, NQ);  // V of the node
+  store_upper<T, NCH, NQ>(a, p, lrow, 0);   // R of the survivor
   __syncthreads();
-  if (threadIdx.x < kMaxB) p.tau_node[(int64_t)right * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : 0.0;
+  if (threadIdx.x < kMaxB) p.tau_node[(int64_t)right * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : T(0);
   __syncthreads();
 }
 
 // Last-arriver ticket on node `node`; true when this workgroup arrived second
 // (and must perform the elimination).  Publishes this workgroup's prior global
 // stores before the ticket and acquires the partner's after it.
-__device__ __forceinline__ bool arrive(const PanelParams &p, int node, PanelSmem &sm) {
+template <class T>
+__device__ __forceinline__ bool arrive(const PanelParamsT<T> &p, int node, PanelSmem<T> &sm) {
   fence_release();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -271,12 +286,12 @@ __device__ __forceinline__ bool arrive(const PanelParams &p, int node, PanelSmem
 
 // The leaves leaf0 .. leaf0 + lpw - 1 of panel p and the part of its tree
 // this workgroup ends up holding (levels 1-3).
-template <int RPT, int NQ>
-__device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
-  __shared__ PanelSmem sm;
+template <class T, int RPT, int NQ>
+__device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
+  __shared__ PanelSmem<T> sm;
   constexpr int NCH = (RPT > 2 * NQ) ? RPT : 2 * NQ;
   constexpr int H = 16 * RPT;
-  double a[NCH][NQ];
+  T a[NCH][NQ];
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
   const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
@@ -291,9 +306,9 @@ __device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
     if (full) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const double *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
+        const T *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
 #pragma unroll
-        for (int i = 0; i < NCH; ++i) a[i][q] = (i < RPT) ? colp[16 * i] : 0.0;
+        for (int i = 0; i < NCH; ++i) a[i][q] = (i < RPT) ? colp[16 * i] : T(0);
       }
     } else {
 #pragma unroll
@@ -302,15 +317,15 @@ __device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
         for (int q = 0; q < NQ; ++q) {
           const int64_t grow = row0 + 16 * i + r;
           const int col = c + 16 * q;
-          a[i][q] = (i < RPT && grow < p.m && col < p.b) ? *pan(p, grow, col) : 0.0;
+          a[i][q] = (i < RPT && grow < p.m && col < p.b) ? *pan(p, grow, col) : T(0);
         }
     }
     __syncthreads();
-    householder_steps<NCH, NQ, RPT, false>(a, p.b, sm);
+    householder_steps<T, NCH, NQ, RPT, false>(a, p.b, sm);
     if (full) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        double *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
+        T *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) colp[16 * i] = a[i][q];
       }
@@ -326,7 +341,7 @@ __device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
     }
     __syncthreads();
     if (threadIdx.x < kMaxB)
-      p.tau_leaf[(int64_t)leaf * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : 0.0;
+      p.tau_leaf[(int64_t)leaf * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : T(0);
     __syncthreads();
 
     // ---- levels 2 and 3: climb the binary tree from this leaf
@@ -341,24 +356,24 @@ __device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
           break;
         }
         if (!arrive(p, partner, sm)) return;         // the sibling's workgroup finishes the node
-        combine<NCH, NQ>(a, p, rt, partner, H, sm);
+        combine<T, NCH, NQ>(a, p, rt, partner, H, sm);
       } else {  // right child: node id rt, left sibling rt - half
         const int left = rt - half;
         if (left < leaf0) {
           if (!arrive(p, rt, sm)) return;
         }
-        combine<NCH, NQ>(a, p, left, rt, H, sm);
+        combine<T, NCH, NQ>(a, p, left, rt, H, sm);
         rt = left;
       }
     }
     if (!go_on) continue;
     // ---- root: make the diagonal non-negative, R <- D R, record D
     __syncthreads();
-    load_r<NCH, NQ>(a, p, 0, 0);
+    load_r<T, NCH, NQ>(a, p, 0, 0);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
       const int row = 16 * i + r;
-      if (c == r && row < p.b) sm.dsign[row] = (a[i][i] < 0.0) ? -1.0 : 1.0;
+      if (c == r && row < p.b) sm.dsign[row] = (a[i][i] < T(0)) ? T(-1) : T(1);
     }
     __syncthreads();
 #pragma unroll
@@ -368,7 +383,7 @@ __device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
         const int row = 16 * i + r, col = c + 16 * q;
         if (row <= col && col < p.b) a[i][q] *= sm.dsign[row];
       }
-    store_upper<NCH, NQ>(a, p, 0, 0);
+    store_upper<T, NCH, NQ>(a, p, 0, 0);
     if (threadIdx.x < p.b) p.d[threadIdx.x] = sm.dsign[threadIdx.x];
   }
 }
@@ -376,16 +391,17 @@ __device__ __forceinline__ void panel_body(const PanelParams p, int leaf0) {
 
 template <int RPT, int NQ>
 __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) {
-  panel_body<RPT, NQ>(p, blockIdx.x * p.lpw);
+  panel_body<double, RPT, NQ>(p, blockIdx.x * p.lpw);
 }
 
 // Many independent panels in one launch: workgroup i takes problem
 // items[i].x, leaves from items[i].y on (each problem with its own tickets).
-template <int RPT, int NQ>
-__global__ void __launch_bounds__(kThreads, 2) tsqr_panel_batched_kernel(const PanelParams *probs, const int2 *items) {
+template <class T, int RPT, int NQ>
+__global__ void __launch_bounds__(kThreads, 2) tsqr_panel_batched_kernel(const PanelParamsT<T> *probs,
+                                                                        const int2 *items) {
   const int2 it = items[blockIdx.x];
-  const PanelParams p = probs[__builtin_amdgcn_readfirstlane(it.x)];
-  panel_body<RPT, NQ>(p, __builtin_amdgcn_readfirstlane(it.y));
+  const PanelParamsT<T> p = probs[__builtin_amdgcn_readfirstlane(it.x)];
+  panel_body<T, RPT, NQ>(p, __builtin_amdgcn_readfirstlane(it.y));
 }
 
 template <int RPT, int NQ>
@@ -406,19 +422,31 @@ hipError_t launch_panel_nq(const PanelParams &p, hipStream_t s) {
   }
 }
 
-template <int RPT, int NQ>
-hipError_t launch_batched_t(const PanelParams *probs, const int2 *items, int nitems, hipStream_t s) {
-  hipLaunchKernelGGL((tsqr_panel_batched_kernel<RPT, NQ>), dim3(nitems), dim3(kThreads), 0, s, probs, items);
+template <class T, int RPT, int NQ>
+hipError_t launch_batched_t(const PanelParamsT<T> *probs, const int2 *items, int nitems, hipStream_t s) {
+  hipLaunchKernelGGL((tsqr_panel_batched_kernel<T, RPT, NQ>), dim3(nitems), dim3(kThreads), 0, s, probs, items);
   return hipGetLastError();
 }
 
-template <int RPT>
-hipError_t launch_batched_nq(int nq, const PanelParams *probs, const int2 *items, int nitems, hipStream_t s) {
+template <class T, int RPT>
+hipError_t launch_batched_nq(int nq, const PanelParamsT<T> *probs, const int2 *items, int nitems, hipStream_t s) {
   switch (nq) {
-    case 1: return launch_batched_t<RPT, 1>(probs, items, nitems, s);
-    case 2: return launch_batched_t<RPT, 2>(probs, items, nitems, s);
-    case 3: return launch_batched_t<RPT, 3>(probs, items, nitems, s);
-    case 4: return launch_batched_t<RPT, 4>(probs, items, nitems, s);
+    case 1: return launch_batched_t<T, RPT, 1>(probs, items, nitems, s);
+    case 2: return launch_batched_t<T, RPT, 2>(probs, items, nitems, s);
+    case 3: return launch_batched_t<T, RPT, 3>(probs, items, nitems, s);
+    case 4: return launch_batched_t<T, RPT, 4>(probs, items, nitems, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class T>
+hipError_t launch_batched(const PanelParamsT<T> *probs, const int2 *items, int nitems, int leaf_rows, int nq,
+                          hipStream_t s) {
+  if (nitems < 1 || nq < 1 || nq > 4) return hipErrorInvalidValue;
+  switch (leaf_rows) {
+    case 64: return launch_batched_nq<T, 4>(nq, probs, items, nitems, s);
+    case 128: return launch_batched_nq<T, 8>(nq, probs, items, nitems, s);
+    case 256: return launch_batched_nq<T, 16>(nq, probs, items, nitems, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -427,13 +455,12 @@ hipError_t launch_batched_nq(int nq, const PanelParams *probs, const int2 *items
 
 hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items, int nitems, int leaf_rows, int nq,
                                      hipStream_t s) {
-  if (nitems < 1 || nq < 1 || nq > 4) return hipErrorInvalidValue;
-  switch (leaf_rows) {
-    case 64: return launch_batched_nq<4>(nq, probs, items, nitems, s);
-    case 128: return launch_batched_nq<8>(nq, probs, items, nitems, s);
-    case 256: return launch_batched_nq<16>(nq, probs, items, nitems, s);
-    default: return hipErrorInvalidValue;
-  }
+  return launch_batched<double>(probs, items, nitems, leaf_rows, nq, s);
+}
+
+hipError_t launch_tsqr_panel_batched(const PanelParams32 *probs, const int2 *items, int nitems, int leaf_rows, int nq,
+                                     hipStream_t s) {
+  return launch_batched<float>(probs, items, nitems, leaf_rows, nq, s);
 }
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s) {

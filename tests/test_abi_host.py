@@ -111,7 +111,7 @@ def test_batched_argument_validation_without_device():
     assert call([10, 20], [2, 0], [10, 20], ptrs=[A.value, None]) == 1  # n = 0 may be NULL: only the handle fails
     assert call([10, 20], [2, 30], [10, 20]) == 4                     # m < n
     assert call([100], [65], [100]) == 4                              # n > 64
-    assert call([100], [8], [100], dt=caqr.F32) == 4                  # FP32 not built
+    assert call([100], [8], [100], dt=caqr.F32) == 1                  # FP32 valid: NULL handle
     assert call([100], [8], [100], dt=7) == 1                         # unknown dtype
     bad = caqr.TreeOpts(100, 0, 0, 0)
     assert call([100], [8], [100], opts=ctypes.byref(bad)) == 1       # leaf_rows not 64/128/256

@@ -121,12 +121,15 @@ def test_extreme_scaling_rescue_path():
     """Entries near the underflow/overflow limits: the scaled norm path keeps R exact up to rounding."""
     require_gpu()
     A = inputs.gaussian(3000, 16, 81)
+    R0 = tsqr_gpu(A)[1]
     for k in (-1000, 1000):  # squares under/overflow, entries and products do not
         As = np.ldexp(A, k)
         R = tsqr_gpu(As)[1]
         Rref = oracle.qr_r(As)
         assert np.all(np.isfinite(R))
         assert oracle.rel_fro(np.ldexp(R, -k), np.ldexp(Rref, -k)) <= 1e-11, k
+        # the rescaled sums keep the unscaled summation order: still exact
+        assert np.array_equal(R, np.ldexp(R0, k)), k
     # subnormal entries keep ~14 significant bits and the updates round at the
     # subnormal spacing, so only finiteness and agreement to 1e-2 are meaningful
     As = np.ldexp(A, -1060)
