@@ -120,6 +120,103 @@ def batched_line(dtype_name: str):
         "timed": "one tsqr_factor_batched call incl. planning and table upload (HIP events)"}
 
 
+def served_lines(rates=(200, 500, 1000, 2000), duration=2.0, workers=8, pool=512, budget=64 << 30,
+                 eta_sample=8):
+    """Served least-squares stream: Poisson arrivals at each rate for `duration`
+    seconds over a cached pool of problems (m log-uniform in [1024, 262144], n
+    in [16, 512], kappa in [1e2, 1e6]); latency = completion - scheduled
+    arrival.  The same stream through one worker is the plain (one solve at a
+    time) reference.  A rate is skipped for a configuration once a lower rate
+    left it overloaded (p99 above 5 s)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1303_5837_amd import caqr, inputs
+
+    seed = inputs.SEEDS["served_ls"]
+    ms, ns, ks = inputs.served_ls_requests(pool)
+    t_pool = time.perf_counter()
+    P = [(inputs.conditioned_device(int(m), int(n), float(k), seed * 1000003 + i),
+          inputs.gaussian_device(int(m), 1, seed * 1000003 + 500000 + i)) for i, (m, n, k) in enumerate(zip(ms, ns, ks))]
+    torch.cuda.synchronize()
+    t_pool = time.perf_counter() - t_pool
+    flops = np.array([2.0 * m * n * n - 2.0 * n ** 3 / 3 for m, n in zip(ms, ns)])
+
+    def eta(A, x, b):
+        v = torch.ones(A.shape[1], 1, dtype=torch.float64, device=A.device)
+        for _ in range(30):  # power iteration for ||A||_2
+            v = A.t() @ (A @ v)
+            v = v / torch.linalg.norm(v)
+        na = float(torch.linalg.norm(A @ v))
+        r = b - A @ x
+        return float(torch.linalg.norm(A.t() @ r)) / (na * (na * float(torch.linalg.norm(x)) + float(torch.linalg.norm(b))))
+
+    out = {"pool": pool, "pool_build_s": round(t_pool, 1), "duration_s": duration, "budget_bytes": budget,
+           "request_gflop_mean": round(float(flops.mean()) / 1e9, 3)}
+    for label, w in (("served", workers), ("plain", 1)):
+        S = caqr.Server(workers=w, budget_bytes=budget)
+        for i in range(2 * w):  # first use of every worker's handle
+            A, B = P[i % pool]
+            X = torch.empty((1, A.shape[1]), dtype=torch.float64, device="cuda").t()
+            S.wait(S.submit(A, B, X))
+        per = {}
+        overloaded = False
+        for rate in rates:
+            if overloaded:
+                per[str(rate)] = "skipped (overloaded at a lower rate)"
+                continue
+            arr = inputs.poisson_arrivals(float(rate), duration, seed * 7919 + rate)
+            pick = np.random.default_rng(seed * 31 + rate).integers(0, pool, len(arr))
+            tickets = [None] * len(arr)
+            ends = np.zeros(len(arr), dtype=np.int64)
+            status = np.zeros(len(arr), dtype=np.int64)
+            keep = {}
+            ready = threading.Semaphore(0)
+
+            def waiter():
+                for j in range(len(arr)):
+                    ready.acquire()
+                    st, _, _, _, end = S.wait(tickets[j])
+                    ends[j], status[j] = end, st
+
+            th = threading.Thread(target=waiter)
+            th.start()
+            t0 = time.monotonic_ns()
+            for j, (ta, pi) in enumerate(zip(arr, pick)):
+                target = t0 + int(ta * 1e9)
+                while True:
+                    dt = (target - time.monotonic_ns()) / 1e9
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 0.002))
+                A, B = P[pi]
+                X = torch.empty((1, A.shape[1]), dtype=torch.float64, device="cuda").t()
+                tickets[j] = S.submit(A, B, X)
+                if j < eta_sample:
+                    keep[j] = X
+                ready.release()
+            th.join()
+            lat = (ends - (t0 + (arr * 1e9).astype(np.int64))) / 1e6
+            span = (ends.max() - t0) / 1e9
+            etas = [eta(P[pick[j]][0], keep[j], P[pick[j]][1]) for j in keep]
+            per[str(rate)] = {
+                "requests": int(len(arr)), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3),
+                "solves_per_s": round(len(arr) / span, 1),
+                "sustained_gflops": round(float(flops[pick].sum()) / span / 1e9, 1),
+                "status_ok": int((status == 0).sum()),
+                "eta_sample_max": float(max(etas)) if etas else None,
+                "eta_sample_le_1e-12": float(np.mean([e <= 1e-12 for e in etas])) if etas else None}
+            overloaded = per[str(rate)]["p99_ms"] > 5000.0
+        S.close()
+        out[label] = {"workers": w, "rates": per}
+    del P
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +355,7 @@ def main():
         # plans from the autotuner; one step = one tsqr_factor_batched call
         sec["batched_tsqr_2000_uneven"] = batched_line("f64")
         sec["batched_tsqr_2000_uneven_f32"] = batched_line("f32")
+        sec["served_ls"] = served_lines()
         out["secondary"] = sec
 
     if not args.no_cpu_baseline:

@@ -275,6 +275,60 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt);
 /* The plan a batched call with opts == NULL would use for an m-by-n problem. */
 caqr_status_t caqr_batch_plan_for(caqr_handle_t h, int64_t m, int64_t n, caqr_dtype_t dt, caqr_tree_opts_t *plan);
 
+/* ------------------------------------------------------------------------ */
+/* Served least-squares stream.  Independent requests min ||A_i X_i - B_i||   */
+/* (the solve of ls_solve, Section 3 of the paper for the factorization) are */
+/* run concurrently on one GPU: `workers` host threads, each with its own    */
+/* handle and non-blocking stream, take requests in arrival order as soon as */
+/* one is free and the request's device footprint fits in the budget.  The   */
+/* footprint is a copy of A (m x n), a copy of B (m x nrhs) and the factors' */
+/* workspace, all carved from one device allocation made at creation, so no */
+/* device memory is allocated or freed while serving.  A request's result is */
+/* bitwise that of ls_solve on the same problem, whatever else is served.    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct caqr_server_s *caqr_server_t;
+
+typedef struct {
+  int32_t device;        /* GPU ordinal */
+  int32_t workers;       /* concurrent requests, 1 .. 64 */
+  uint64_t budget_bytes; /* device memory for the requests in flight (>= 256) */
+  int64_t reserved;      /* must be 0 */
+} caqr_server_opts_t;
+
+typedef struct {
+  int64_t submit_ns; /* host steady clock (CLOCK_MONOTONIC on Linux), nanoseconds */
+  int64_t start_ns;  /* admitted: a worker and the memory were free */
+  int64_t end_ns;    /* X written and the request's stream idle */
+} caqr_request_times_t;
+
+/* Allocate the budget on the device, create the workers' handles and streams,
+   start the workers.  Errors: CAQR_ERR_INVALID_VALUE (NULL arguments, workers
+   outside 1..64, budget < 256, reserved != 0); CAQR_ERR_DEVICE (no such GPU);
+   CAQR_ERR_ALLOC. */
+caqr_status_t caqr_server_create(const caqr_server_opts_t *o, caqr_server_t *S);
+
+/* Queue the solve of min ||A X - B||_F for an m-by-n A (m >= n, column-major,
+   lda) and m-by-nrhs B (ldb); the n-by-nrhs solution goes to X (ldx >= n).
+   A, B and X are device memory owned by the caller: A and B are only read (the
+   server works on copies) and must stay valid and unchanged, and X unused,
+   until caqr_server_wait returns for the ticket.  Returns at once.  Errors
+   (nothing is queued): CAQR_ERR_INVALID_VALUE for negative sizes, leading
+   dimensions below max(1, m) (max(1, n) for ldx), NULL pointers with nonzero
+   sizes, a NULL ticket or server; CAQR_ERR_NOT_SUPPORTED for m < n;
+   CAQR_ERR_ALLOC when the request's footprint exceeds the whole budget. */
+caqr_status_t caqr_server_submit(caqr_server_t S, int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                                 const double *B, int64_t ldb, double *X, int64_t ldx, int64_t *ticket);
+
+/* Block until the request has finished; fill info (status, and the first
+   zero pivot for CAQR_ERR_SINGULAR) and times (either may be NULL), and
+   release the ticket.  Returns the request's status (as ls_solve would), or
+   CAQR_ERR_INVALID_VALUE for an unknown or already released ticket. */
+caqr_status_t caqr_server_wait(caqr_server_t S, int64_t ticket, caqr_ls_info_t *info, caqr_request_times_t *times);
+
+/* Finish every queued request, stop the workers and free the server. */
+caqr_status_t caqr_server_destroy(caqr_server_t S);
+
 #ifdef __cplusplus
 }
 #endif

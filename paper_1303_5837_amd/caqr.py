@@ -67,6 +67,15 @@ class LsInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("index", ctypes.c_int64)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("workers", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64),
+                ("reserved", ctypes.c_int64)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_int64), ("start_ns", ctypes.c_int64), ("end_ns", ctypes.c_int64)]
+
+
 _lib_obj = None
 _lib_lock = threading.Lock()
 
@@ -75,7 +84,7 @@ EXPORTS = [
     "caqr_status_string", "caqr_device_count", "tsqr_factor", "caqr_factor", "apply_q", "caqr_factors_destroy",
     "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_trace_read",
     "tsqr_factor_batched", "caqr_batch_destroy", "caqr_batch_get_plan", "caqr_batch_get_signs", "caqr_tune_batched",
-    "caqr_batch_plan_for",
+    "caqr_batch_plan_for", "caqr_server_create", "caqr_server_submit", "caqr_server_wait", "caqr_server_destroy",
 ]
 
 
@@ -114,6 +123,10 @@ def _lib():
         L.caqr_batch_get_signs.argtypes = [vp, i64, dp]
         L.caqr_tune_batched.argtypes = [vp, i32]
         L.caqr_batch_plan_for.argtypes = [vp, i64, i64, i32, ctypes.POINTER(TreeOpts)]
+        L.caqr_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+        L.caqr_server_submit.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(i64)]
+        L.caqr_server_wait.argtypes = [vp, i64, ctypes.POINTER(LsInfo), ctypes.POINTER(RequestTimes)]
+        L.caqr_server_destroy.argtypes = [vp]
         for name in EXPORTS:
             if name not in ("caqr_status_string",):
                 getattr(L, name).restype = ctypes.c_int
@@ -377,3 +390,46 @@ def batch_plan_for(m: int, n: int, device: int = 0, dtype=torch.float64):
     o = TreeOpts()
     _check(_lib().caqr_batch_plan_for(h.ptr, m, n, _dtype_code(dtype), ctypes.byref(o)), "caqr_batch_plan_for")
     return int(o.leaf_rows), int(o.leaves_per_wg)
+
+
+class Server:
+    """Served least-squares stream (``caqr_server_*``): requests solved
+    concurrently by ``workers`` streams within a device memory budget."""
+
+    def __init__(self, workers: int = 8, budget_bytes: int = 8 << 30, device: int = 0):
+        self._s = ctypes.c_void_p()
+        o = ServerOpts(device, workers, budget_bytes, 0)
+        _check(_lib().caqr_server_create(ctypes.byref(o), ctypes.byref(self._s)), "caqr_server_create")
+        self._keep = {}
+
+    def submit(self, A: torch.Tensor, B: torch.Tensor, X: torch.Tensor) -> int:
+        """Queue min ||A X - B|| (A, B read only; X receives the n-by-nrhs
+        solution).  The tensors are kept alive until ``wait``."""
+        m, n = A.shape
+        t = ctypes.c_int64()
+        _check(_lib().caqr_server_submit(self._s, m, n, B.shape[1], ctypes.c_void_p(A.data_ptr()), _ld(A),
+                                         ctypes.c_void_p(B.data_ptr()), _ld(B), ctypes.c_void_p(X.data_ptr()),
+                                         _ld(X), ctypes.byref(t)), "caqr_server_submit")
+        self._keep[t.value] = (A, B, X)
+        return t.value
+
+    def wait(self, ticket: int):
+        """(status, index, submit_ns, start_ns, end_ns) of a finished request."""
+        info, tm = LsInfo(), RequestTimes()
+        code = _lib().caqr_server_wait(self._s, ticket, ctypes.byref(info), ctypes.byref(tm))
+        self._keep.pop(ticket, None)
+        if code not in (0, 5, 6):
+            _check(code, "caqr_server_wait")
+        return int(info.status), int(info.index), int(tm.submit_ns), int(tm.start_ns), int(tm.end_ns)
+
+    def close(self):
+        if self._s:
+            _lib().caqr_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

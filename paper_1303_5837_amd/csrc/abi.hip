@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/caqr.h"
+#include "abi_internal.hpp"
 #include "kernels.hpp"
 
 using namespace caqr;
@@ -105,6 +106,7 @@ struct caqr_factors_s {
   double *tbuf = nullptr;   // T of all panels (eager for caqr_factor, lazy for tsqr_factor)
   size_t tbuf_bytes = 0;
   bool t_formed = false;
+  bool borrowed = false;    // small/tbuf lent by the caller (a served solve): not freed here
   size_t limit = 0;
 };
 
@@ -195,10 +197,26 @@ int resolve_leaf_rows(const caqr_tree_opts_t *o) {
 
 bool valid_leaf_rows(int h) { return h == 64 || h == 128 || h == 256; }
 
+// Bytes of the tau/d and T buffers of an m-by-n factorization with panel
+// width nb and leaf height leaf_rows (T aligned to 256 bytes after tau/d).
+size_t factor_ws_bytes(int64_t m, int64_t n, int64_t nb, int leaf_rows, size_t *small_out) {
+  size_t small_doubles = 0, t_doubles = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += nb) {
+    const int L = ceil_div(m - c0, leaf_rows);
+    small_doubles += (size_t)L * 2 * kNbMax + kNbMax;
+    t_doubles += (size_t)L * 2 * kNbMax * kNbMax;
+  }
+  const size_t small = (small_doubles * sizeof(double) + 255) & ~(size_t)255;
+  if (small_out) *small_out = small;
+  return small + t_doubles * sizeof(double);
+}
+
 // Plan the panels of an m-by-n factorization with panel width nb and build
-// the factors object (buffers for tau, d and optionally T).
+// the factors object (buffers for tau, d and optionally T).  With ws, the
+// buffers are carved from it (factor_ws_bytes bytes, 256-byte aligned) and
+// stay the lender's.
 caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda, int leaf_rows,
-                           int lpw, bool eager_t, caqr_factors_t *out) {
+                           int lpw, bool eager_t, void *ws, caqr_factors_t *out) {
   caqr_factors_s *F = new (std::nothrow) caqr_factors_s;
   if (!F) return CAQR_ERR_ALLOC;
   F->device = h->device;
@@ -225,11 +243,17 @@ caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, do
   const size_t small_bytes = small_doubles * sizeof(double);
   const size_t t_bytes = t_doubles * sizeof(double);
   const size_t need = small_bytes + (eager_t ? t_bytes : 0);
-  if (h->ws_limit && need > h->ws_limit) {
+  if (ws) {
+    size_t small_al = 0;
+    (void)factor_ws_bytes(m, n, nb, leaf_rows, &small_al);
+    F->borrowed = true;
+    F->small = static_cast<double *>(ws);
+    F->tbuf = reinterpret_cast<double *>(static_cast<char *>(ws) + small_al);
+  } else if (h->ws_limit && need > h->ws_limit) {
     delete F;
     return CAQR_ERR_ALLOC;
   }
-  if (small_bytes && hipMalloc(&F->small, small_bytes) != hipSuccess) {
+  if (!F->borrowed && small_bytes && hipMalloc(&F->small, small_bytes) != hipSuccess) {
     delete F;
     return CAQR_ERR_ALLOC;
   }
@@ -244,7 +268,7 @@ caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, do
   }
   F->tbuf_bytes = t_bytes;
   if (eager_t && t_bytes) {
-    if (hipMalloc(&F->tbuf, t_bytes) != hipSuccess) {
+    if (!F->borrowed && hipMalloc(&F->tbuf, t_bytes) != hipSuccess) {
       (void)hipFree(F->small);
       delete F;
       return CAQR_ERR_ALLOC;
@@ -436,12 +460,12 @@ caqr_status_t check_opts(const caqr_tree_opts_t *o) {
 }
 
 caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
-                          const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr) {
+                          const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr, void *ws = nullptr) {
   const int hr = resolve_leaf_rows(opts);
   const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : (tsqr ? 4 : 1);
   DeviceGuard g(h->device);
   caqr_factors_t f = nullptr;
-  caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, &f);
+  caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, ws, &f);
   if (st) return st;
   if (n > 0) {
     st = run_factorization(h, f, !tsqr);
@@ -790,6 +814,10 @@ caqr_status_t apply_q(caqr_handle_t h, caqr_factors_t F, caqr_op_t op, int64_t k
 
 caqr_status_t caqr_factors_destroy(caqr_factors_t F) {
   if (!F) return CAQR_ERR_INVALID_VALUE;
+  if (F->borrowed) {  // the lender orders reuse of its buffers after the work
+    delete F;
+    return CAQR_SUCCESS;
+  }
   DeviceGuard g(F->device);
   // the buffers may still be read by enqueued kernels: wait for the device first
   (void)hipDeviceSynchronize();
@@ -835,7 +863,31 @@ caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, doub
   if ((n > 0 && !A) || (nrhs > 0 && !B)) return CAQR_ERR_INVALID_VALUE;
   if (o && o->reserved) return CAQR_ERR_INVALID_VALUE;
   if (m < n) return CAQR_ERR_NOT_SUPPORTED;
+  if (n > INT32_MAX || m / std::max<int64_t>(n, 1) > ((int64_t)1 << 40)) return CAQR_ERR_NOT_SUPPORTED;
   if (!h) return CAQR_ERR_INVALID_VALUE;
+  return caqr::ls_solve_ws(h, m, n, nrhs, A, lda, B, ldb, nullptr, info);
+}
+
+}  // extern "C"
+
+namespace caqr {
+
+// The plan of a least-squares solve depends only on (m, n): TSQR (leaf 256,
+// four leaves per workgroup) for n <= 64, else CAQR with 64-column panels.
+size_t ls_workspace_bytes(int64_t m, int64_t n) {
+  if (n <= 0) return 0;
+  return factor_ws_bytes(m, n, n <= kNbMax ? std::max<int64_t>(n, 1) : kNbMax, 256, nullptr);
+}
+
+caqr_status_t reserve_tickets(caqr_handle_t h, size_t counters) {
+  DeviceGuard g(h->device);
+  return ensure_tickets(h, counters);
+}
+
+// Arguments already validated.  With ws (ls_workspace_bytes(m, n) bytes), no
+// device memory is allocated or freed.
+caqr_status_t ls_solve_ws(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
+                          int64_t ldb, void *ws, caqr_ls_info_t *info) {
   if (info) {
     info->status = CAQR_SUCCESS;
     info->index = 0;
@@ -843,8 +895,8 @@ caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, doub
   if (n == 0 || nrhs == 0) return CAQR_SUCCESS;
   DeviceGuard g(h->device);
   caqr_factors_t F = nullptr;
-  caqr_status_t st = (n <= kNbMax) ? tsqr_factor(h, m, n, A, lda, nullptr, &F)
-                                   : caqr_factor(h, m, n, kNbMax, A, lda, nullptr, &F);
+  caqr_status_t st = (n <= kNbMax) ? factor_impl(h, m, n, std::max<int64_t>(n, 1), A, lda, nullptr, &F, true, ws)
+                                   : factor_impl(h, m, n, kNbMax, A, lda, nullptr, &F, false, ws);
   if (st) return st;
   st = apply_q(h, F, CAQR_OP_T, nrhs, B, ldb);
   if (!st && launch_trsm_upper(A, lda, n, B, ldb, nrhs, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
@@ -867,6 +919,10 @@ caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, doub
   }
   return num;
 }
+
+}  // namespace caqr
+
+extern "C" {
 
 caqr_status_t tsqr_factor_batched(caqr_handle_t h, int64_t batch, const int64_t *m, const int64_t *n,
                                   void *const *A, const int64_t *lda, caqr_dtype_t dt,

@@ -1,0 +1,25 @@
+// Library-internal entry points shared by the C ABI and the request server.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/caqr.h"
+
+namespace caqr {
+
+// Device bytes a least-squares solve of an m-by-n problem needs for its
+// factors (tau, signs and compact-WY T of every panel), when lent to it.
+size_t ls_workspace_bytes(int64_t m, int64_t n);
+
+// Least-squares solve with validated arguments on the handle's stream.  With
+// ws (ls_workspace_bytes bytes of device memory, 256-byte aligned) the solve
+// allocates and frees no device memory; without, it allocates its own.
+// Returns after the solve has finished (it reads back the status words).
+caqr_status_t ls_solve_ws(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
+                          int64_t ldb, void *ws, caqr_ls_info_t *info);
+
+// Pre-size the handle's ticket counters (device-tree synchronization).
+caqr_status_t reserve_tickets(caqr_handle_t h, size_t counters);
+
+}  // namespace caqr

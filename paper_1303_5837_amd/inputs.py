@@ -62,3 +62,38 @@ def gaussian_device(m: int, n: int, seed: int, device="cuda"):
     g = torch.Generator(device=device)
     g.manual_seed(seed)
     return torch.randn((n, m), generator=g, dtype=torch.float64, device=device).t()
+
+
+def served_ls_requests(count: int = 512, seed: int = SEEDS["served_ls"]):
+    """Request mix of the served least-squares stream: m log-uniform in
+    [1024, 262144], n log-uniform in [16, 512], condition number kappa
+    log-uniform in [1e2, 1e6]."""
+    rng = np.random.default_rng(seed)
+    m = log_uniform_int(rng, 1024, 262144, count)
+    n = np.minimum(log_uniform_int(rng, 16, 512, count), m)
+    kappa = np.exp(rng.uniform(np.log(1e2), np.log(1e6), count))
+    return m, n, kappa
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of the given rate on [0, duration)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, int(rate * duration * 1.5) + 16))
+    return t[t < duration]
+
+
+def conditioned_device(m: int, n: int, kappa: float, seed: int, device="cuda"):
+    """A = G diag(s) V^T on the device, column-major: G an m-by-n N(0,1) draw
+    (torch's seeded generator), s geometric from 1 to 1/kappa, V the orthogonal
+    factor of an n-by-n N(0,1) draw (numpy's QR); the singular values of A
+    spread over about kappa times those of G."""
+    import torch
+
+    G = gaussian_device(m, n, seed, device)
+    rng = np.random.default_rng(seed)
+    V = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    s = geometric_singular_values(n, kappa)
+    W = torch.as_tensor(np.ascontiguousarray((V * s).T), device=device)  # diag(s) V^T, row-major n x n
+    A = torch.empty((n, m), dtype=torch.float64, device=device).t()
+    torch.matmul(G, W, out=A)
+    return A

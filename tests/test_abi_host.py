@@ -122,3 +122,28 @@ def test_batched_argument_validation_without_device():
     assert lib.caqr_batch_get_signs(None, 0, None) == 1
     assert lib.caqr_tune_batched(None, caqr.F64) == 1
     assert lib.caqr_batch_plan_for(None, 100, 8, caqr.F64, None) == 1
+
+
+def test_server_argument_validation_without_device():
+    """caqr_server_create / submit check their arguments before the device."""
+    lib = caqr.library()
+    S = ctypes.c_void_p()
+    bad = [caqr.ServerOpts(0, 0, 1 << 20, 0), caqr.ServerOpts(0, 65, 1 << 20, 0),
+           caqr.ServerOpts(0, 2, 100, 0), caqr.ServerOpts(0, 2, 1 << 20, 1)]
+    for o in bad:
+        assert lib.caqr_server_create(ctypes.byref(o), ctypes.byref(S)) == 1
+    assert lib.caqr_server_create(None, ctypes.byref(S)) == 1
+    assert lib.caqr_server_create(ctypes.byref(caqr.ServerOpts(0, 2, 1 << 20, 0)), None) == 1
+    if caqr.device_count() == 0:
+        assert lib.caqr_server_create(ctypes.byref(caqr.ServerOpts(0, 2, 1 << 20, 0)), ctypes.byref(S)) == 3
+    p = ctypes.c_void_p(0x1000)
+    t = ctypes.c_int64()
+    sub = lib.caqr_server_submit
+    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 10, ctypes.byref(t)) == 1   # valid request, NULL server
+    assert sub(None, 100, 10, 1, p, 99, p, 100, p, 10, ctypes.byref(t)) == 1    # lda < m
+    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 9, ctypes.byref(t)) == 1    # ldx < n
+    assert sub(None, 100, 10, 1, None, 100, p, 100, p, 10, ctypes.byref(t)) == 1  # NULL A
+    assert sub(None, 10, 20, 1, p, 10, p, 10, p, 20, ctypes.byref(t)) == 4      # m < n
+    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 10, None) == 1              # NULL ticket
+    assert lib.caqr_server_wait(None, 1, None, None) == 1
+    assert lib.caqr_server_destroy(None) == 1

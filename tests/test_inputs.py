@@ -26,3 +26,12 @@ def test_batched_sizes_and_singular_values():
     assert m.min() >= 256 and m.max() <= 65536 and set(np.unique(n)) <= {8, 16, 32, 64}
     s = inputs.geometric_singular_values(5, 1e4)
     assert s[0] == 1.0 and abs(s[-1] - 1e-4) < 1e-18 and np.all(np.diff(s) < 0)
+
+
+def test_served_mix_and_arrivals():
+    m, n, k = inputs.served_ls_requests(512)
+    assert m.min() >= 1024 and m.max() <= 262144 and n.min() >= 16 and n.max() <= 512
+    assert np.all(n <= m) and k.min() >= 1e2 and k.max() <= 1e6
+    t = inputs.poisson_arrivals(1000.0, 2.0, 11)
+    assert np.all(np.diff(t) > 0) and t[-1] < 2.0 and 1800 < len(t) < 2200
+    assert np.array_equal(t, inputs.poisson_arrivals(1000.0, 2.0, 11))

@@ -1,0 +1,125 @@
+"""Served least-squares stream: concurrent requests on several streams within a
+device memory budget.  Every served result is bitwise the plain ls_solve result
+of the same problem (the plan depends only on (m, n)), whatever is served
+beside it and however the budget makes requests wait; inputs are only read."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1303_5837_amd import caqr, inputs
+from tests._gpu import banner, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+# TSQR (n <= 64) and CAQR (n > 64) solves, ragged m, several right-hand sides
+MIX = [(3000, 40, 1), (1024, 16, 2), (20000, 200, 1), (5000, 64, 3), (700, 65, 1), (9000, 130, 2),
+       (40000, 24, 1), (2500, 300, 1), (1500, 1, 1), (12345, 100, 2)]
+
+
+def problems(mix, seed):
+    out = []
+    for i, (m, n, k) in enumerate(mix):
+        A = inputs.conditioned_device(m, n, 10.0 ** (2 + i % 5), seed + i)
+        B = inputs.gaussian_device(m, k, seed + 500 + i)
+        out.append((A, B))
+    torch.cuda.synchronize()
+    return out
+
+
+def plain(A, B):
+    dA, dB = A.clone(memory_format=torch.preserve_format), B.clone(memory_format=torch.preserve_format)
+    X, info = caqr.ls_solve(dA, dB)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), info.status
+
+
+def serve(S, probs, order=None):
+    order = range(len(probs)) if order is None else order
+    Xs, tickets = {}, {}
+    for i in order:
+        A, B = probs[i]
+        X = torch.full((B.shape[1], A.shape[1]), np.nan, dtype=torch.float64, device="cuda").t()
+        tickets[i] = S.submit(A, B, X)
+        Xs[i] = X
+    res = {i: S.wait(t) for i, t in tickets.items()}
+    torch.cuda.synchronize()
+    return {i: X.cpu().numpy() for i, X in Xs.items()}, res
+
+
+def test_served_equals_plain_bitwise():
+    require_gpu()
+    probs = problems(MIX, 7100)
+    copies = [(A.clone(), B.clone()) for A, B in probs]
+    ref = [plain(A, B) for A, B in probs]
+    S = caqr.Server(workers=4, budget_bytes=2 << 30)
+    got, res = serve(S, probs)
+    for i, (m, n, k) in enumerate(MIX):
+        banner(f"served {i}: m={m} n={n} nrhs={k} status={res[i][0]}")
+        assert res[i][0] == 0 and ref[i][1] == 0
+        assert np.array_equal(got[i], ref[i][0]), (m, n, k)
+        assert res[i][2] <= res[i][3] <= res[i][4]
+    for (A, B), (A0, B0) in zip(probs, copies):  # inputs are only read
+        assert torch.equal(A, A0) and torch.equal(B, B0)
+    # the same problems again, in another order and with another worker count
+    S2 = caqr.Server(workers=7, budget_bytes=3 << 30)
+    got2, _ = serve(S2, probs, order=list(reversed(range(len(probs)))))
+    for i in range(len(MIX)):
+        assert np.array_equal(got2[i], ref[i][0])
+    S.close()
+    S2.close()
+
+
+def test_served_backward_error():
+    require_gpu()
+    probs = problems(MIX[:6], 7200)
+    S = caqr.Server(workers=3, budget_bytes=1 << 30)
+    got, res = serve(S, probs)
+    for i, (A, B) in enumerate(probs):
+        assert res[i][0] == 0
+        Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+        eta = oracle.ls_eta(Ah, got[i], Bh)
+        banner(f"served {i}: eta {eta:.2e}")
+        assert eta <= 1e-12
+    S.close()
+
+
+def test_tight_budget_admits_in_order():
+    """A budget that holds one large request at a time: requests wait for
+    memory, start in arrival order, and still give the plain results."""
+    require_gpu()
+    mix = [(30000, 120, 1)] * 3 + [(2000, 20, 1), (30000, 120, 1), (4000, 50, 1)]
+    probs = problems(mix, 7300)
+    ref = [plain(A, B)[0] for A, B in probs]
+    # A and B copies plus a bound on the factors' workspace (T: about 16 MB here):
+    # 1.2 times that holds one large request with the small ones, never two large
+    one = 30000 * 120 * 8 + 30000 * 8 + (20 << 20)
+    S = caqr.Server(workers=4, budget_bytes=int(one * 1.2))
+    got, res = serve(S, probs)
+    starts = [res[i][3] for i in range(len(mix))]
+    assert starts == sorted(starts)
+    for i in range(len(mix)):
+        assert np.array_equal(got[i], ref[i])
+    S.close()
+
+
+def test_request_errors():
+    require_gpu()
+    S = caqr.Server(workers=2, budget_bytes=1 << 20)
+    A = inputs.gaussian_device(4000, 100, 7400)
+    B = inputs.gaussian_device(4000, 1, 7401)
+    X = torch.empty((1, 100), dtype=torch.float64, device="cuda").t()
+    with pytest.raises(caqr.CaqrError) as e:  # footprint above the whole budget
+        S.submit(A, B, X)
+    assert e.value.code == 2
+    Z = A[:, :20].clone(memory_format=torch.preserve_format)
+    Z[:, 5] = 0.0
+    Xz = torch.empty((1, 20), dtype=torch.float64, device="cuda").t()
+    S2 = caqr.Server(workers=2, budget_bytes=64 << 20)
+    t = S2.submit(Z, B, Xz)
+    st, idx, *_ = S2.wait(t)
+    assert st == 5 and idx == 5
+    with pytest.raises(caqr.CaqrError):
+        S2.wait(t)  # released
+    S.close()
+    S2.close()
