@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -90,10 +91,19 @@ struct caqr_batch_s {
     int64_t prob0, nprob, item0, nitem, rows, leaves;
   };
   std::vector<Group> groups;
+  // device tree levels: round k holds every problem's k-th level above its
+  // workgroups' leaves, one launch per (round, nq): nodes (problem, left
+  // slot, right slot, leaf rows | root << 16)
+  std::vector<int4> nodes;
+  struct Level {
+    int nq;
+    int64_t node0, nnode;
+  };
+  std::vector<Level> levels;
   void *small = nullptr;                // tau_leaf, tau_node, d of every problem (batch's type)
-  unsigned *tickets = nullptr;          // one counter per leaf of every problem
   void *probs_dev = nullptr;            // PanelParams or PanelParams32 table
   int2 *items_dev = nullptr;
+  int4 *nodes_dev = nullptr;
 };
 
 struct caqr_factors_s {
@@ -541,8 +551,8 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
   B->n.assign(n, n + batch);
   B->plan.resize(batch);
   B->d_off.assign(batch, -1);
-  std::vector<int64_t> L(batch, 0), tau_off(batch, 0), tick_off(batch, 0);
-  int64_t small_elems = 0, ticket_count = 0;
+  std::vector<int64_t> L(batch, 0), tau_off(batch, 0);
+  int64_t small_elems = 0;
   for (int64_t i = 0; i < batch; ++i) {
     caqr_tree_opts_t o = opts ? *opts : default_plan(h, m[i], n[i], dt);
     if (!o.leaf_rows) o.leaf_rows = 256;
@@ -554,11 +564,10 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
     small_elems += 2 * L[i] * kNbMax;
     B->d_off[i] = small_elems;
     small_elems += kNbMax;
-    tick_off[i] = ticket_count;
-    ticket_count += L[i];
   }
   // groups in a fixed order: leaf rows 64/128/256, then nq 1..4
   static const int kLeaf[3] = {64, 128, 256};
+  std::vector<std::array<std::vector<int4>, 4>> round_nodes(32);
   for (int hi = 0; hi < 3; ++hi)
     for (int nq = 1; nq <= 4; ++nq) {
       caqr_batch_s::Group g{kLeaf[hi], nq, (int64_t)B->probs.size(), 0, (int64_t)B->items.size(), 0, 0, 0};
@@ -574,7 +583,18 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
         p.tau_leaf = reinterpret_cast<double *>(tau_off[i]);  // offsets; rebased after allocation
         p.tau_node = reinterpret_cast<double *>(tau_off[i] + L[i] * kNbMax);
         p.d = reinterpret_cast<double *>(B->d_off[i]);
-        p.tickets = reinterpret_cast<unsigned *>(tick_off[i]);
+        p.tickets = nullptr;  // the device levels are separate launches
+        // device levels: pairs (left, left + half) for half = lpw, 2 lpw, ...
+        {
+          const int64_t gidx = (int64_t)B->probs.size();
+          int k = 0;
+          for (int64_t half = p.lpw; half < L[i]; half <<= 1, ++k) {
+            const bool top = 2 * half >= L[i];
+            for (int64_t left = 0; left + half < L[i]; left += 2 * half)
+              round_nodes[(size_t)k][nq - 1].push_back(
+                  int4{(int)gidx, (int)left, (int)(left + half), kLeaf[hi] | ((top ? 1 : 0) << 16)});
+          }
+        }
         const int local = (int)(B->probs.size() - g.prob0);
         for (int64_t w = 0; w * p.lpw < L[i]; ++w) B->items.push_back(int2{local, (int)(w * p.lpw)});
         B->probs.push_back(p);
@@ -585,16 +605,23 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
       g.nitem = (int64_t)B->items.size() - g.item0;
       if (g.nprob) B->groups.push_back(g);
     }
+  for (auto &rd : round_nodes)
+    for (int q = 0; q < 4; ++q) {
+      if (rd[q].empty()) continue;
+      B->levels.push_back(caqr_batch_s::Level{q + 1, (int64_t)B->nodes.size(), (int64_t)rd[q].size()});
+      B->nodes.insert(B->nodes.end(), rd[q].begin(), rd[q].end());
+    }
   const size_t es = elem_size(dt);
   const size_t table_bytes = B->probs.size() * (dt == CAQR_F32 ? sizeof(caqr::PanelParams32) : sizeof(caqr::PanelParams));
-  const size_t bytes = small_elems * es + ticket_count * sizeof(unsigned) + table_bytes + B->items.size() * sizeof(int2);
+  const size_t bytes =
+      small_elems * es + table_bytes + B->items.size() * sizeof(int2) + B->nodes.size() * sizeof(int4);
   if (h->ws_limit && bytes > h->ws_limit) {
     delete B;
     return CAQR_ERR_ALLOC;
   }
   bool ok = true;
   if (small_elems) ok = ok && hipMalloc(&B->small, small_elems * es) == hipSuccess;
-  if (ticket_count) ok = ok && hipMalloc(&B->tickets, ticket_count * sizeof(unsigned)) == hipSuccess;
+  if (!B->nodes.empty()) ok = ok && hipMalloc(&B->nodes_dev, B->nodes.size() * sizeof(int4)) == hipSuccess;
   if (table_bytes) ok = ok && hipMalloc(&B->probs_dev, table_bytes) == hipSuccess;
   if (!B->items.empty()) ok = ok && hipMalloc(&B->items_dev, B->items.size() * sizeof(int2)) == hipSuccess;
   if (!ok) {
@@ -615,7 +642,7 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
       q.tau_leaf = small + reinterpret_cast<intptr_t>(p.tau_leaf);
       q.tau_node = small + reinterpret_cast<intptr_t>(p.tau_node);
       q.d = small + reinterpret_cast<intptr_t>(p.d);
-      q.tickets = B->tickets + reinterpret_cast<intptr_t>(p.tickets);
+      q.tickets = nullptr;
       B->probs32.push_back(q);
     }
     B->probs.clear();
@@ -625,18 +652,16 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
       p.tau_leaf = small + reinterpret_cast<intptr_t>(p.tau_leaf);
       p.tau_node = small + reinterpret_cast<intptr_t>(p.tau_node);
       p.d = small + reinterpret_cast<intptr_t>(p.d);
-      p.tickets = B->tickets + reinterpret_cast<intptr_t>(p.tickets);
     }
-  }
-  if (ticket_count) {
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(256), dim3(256), 0, h->stream, B->tickets, (size_t)ticket_count);
-    ok = hipGetLastError() == hipSuccess;
   }
   if (ok && table_bytes)
     ok = hipMemcpyAsync(B->probs_dev, dt == CAQR_F32 ? (const void *)B->probs32.data() : (const void *)B->probs.data(),
                         table_bytes, hipMemcpyHostToDevice, h->stream) == hipSuccess;
   if (ok && !B->items.empty())
     ok = hipMemcpyAsync(B->items_dev, B->items.data(), B->items.size() * sizeof(int2), hipMemcpyHostToDevice,
+                        h->stream) == hipSuccess;
+  if (ok && !B->nodes.empty())
+    ok = hipMemcpyAsync(B->nodes_dev, B->nodes.data(), B->nodes.size() * sizeof(int4), hipMemcpyHostToDevice,
                         h->stream) == hipSuccess;
   if (!ok) {
     caqr_batch_destroy(B);
@@ -646,7 +671,8 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
   return CAQR_SUCCESS;
 }
 
-// One launch per group, in order, on the handle's stream.
+// One launch per group (leaves and the levels inside workgroups), then one
+// launch per (device level round, nq), in order, on the handle's stream.
 caqr_status_t batch_launch(caqr_handle_t h, caqr_batch_t B) {
   for (size_t gi = 0; gi < B->groups.size(); ++gi) {
     const auto &g = B->groups[gi];
@@ -657,6 +683,17 @@ caqr_status_t batch_launch(caqr_handle_t h, caqr_batch_t B) {
                                         B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, h->stream)
             : launch_tsqr_panel_batched(static_cast<const caqr::PanelParams *>(B->probs_dev) + g.prob0,
                                         B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, h->stream);
+    if (e != hipSuccess) return CAQR_ERR_DEVICE;
+  }
+  for (size_t li = 0; li < B->levels.size(); ++li) {
+    const auto &l = B->levels[li];
+    TraceScope ts(h, CAQR_TRACE_PANEL, (int)li, 0, 16 * l.nq, 0, (int)std::min<int64_t>(l.nnode, INT32_MAX));
+    const hipError_t e =
+        B->dt == CAQR_F32
+            ? launch_tsqr_tree_level(static_cast<const caqr::PanelParams32 *>(B->probs_dev), B->nodes_dev + l.node0,
+                                     (int)l.nnode, l.nq, h->stream)
+            : launch_tsqr_tree_level(static_cast<const caqr::PanelParams *>(B->probs_dev), B->nodes_dev + l.node0,
+                                     (int)l.nnode, l.nq, h->stream);
     if (e != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return CAQR_SUCCESS;
@@ -945,7 +982,7 @@ caqr_status_t caqr_batch_destroy(caqr_batch_t F) {
   DeviceGuard g(F->device);
   if (F->stream) (void)hipStreamSynchronize(F->stream);
   if (F->small) (void)hipFree(F->small);
-  if (F->tickets) (void)hipFree(F->tickets);
+  if (F->nodes_dev) (void)hipFree(F->nodes_dev);
   if (F->probs_dev) (void)hipFree(F->probs_dev);
   if (F->items_dev) (void)hipFree(F->items_dev);
   delete F;

@@ -56,11 +56,16 @@ hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s)
 
 // Independent panels of equal ceil(b/16) = nq and leaf height in one launch:
 // probs (device) holds one PanelParams per problem, items (device) one
-// (problem, first leaf) pair per workgroup.
+// (problem, first leaf) pair per workgroup; each workgroup stops at the tree
+// levels that join its leaves with another workgroup's.
 hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items, int nitems, int leaf_rows, int nq,
                                      hipStream_t s);
 hipError_t launch_tsqr_panel_batched(const PanelParams32 *probs, const int2 *items, int nitems, int leaf_rows, int nq,
                                      hipStream_t s);
+// One device-level tree step of many panels of equal ceil(b/16) = nq: node
+// (problem, left slot, right slot, leaf rows | root << 16) per workgroup.
+hipError_t launch_tsqr_tree_level(const PanelParams *probs, const int4 *nodes, int nnodes, int nq, hipStream_t s);
+hipError_t launch_tsqr_tree_level(const PanelParams32 *probs, const int4 *nodes, int nnodes, int nq, hipStream_t s);
 
 // C <- Q^T C for one panel: leaf updates and the tree bottom-up, then rows
 // 0..b-1 scaled by D.  One workgroup per (leaf, tile), then one launch per

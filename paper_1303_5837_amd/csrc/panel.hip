@@ -284,9 +284,36 @@ __device__ __forceinline__ bool arrive(const PanelParamsT<T> &p, int node, Panel
   return second;
 }
 
+// Root of the tree: make the diagonal non-negative, R <- D R, record D.
+template <class T, int NCH, int NQ>
+__device__ __forceinline__ void finish_root(T (&a)[NCH][NQ], const PanelParamsT<T> &p, PanelSmem<T> &sm) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;
+  const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
+  __syncthreads();
+  load_r<T, NCH, NQ>(a, p, 0, 0);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int row = 16 * i + r;
+    if (c == r && row < p.b) sm.dsign[row] = (a[i][i] < T(0)) ? T(-1) : T(1);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NQ; ++i)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int row = 16 * i + r, col = c + 16 * q;
+      if (row <= col && col < p.b) a[i][q] *= sm.dsign[row];
+    }
+  store_upper<T, NCH, NQ>(a, p, 0, 0);
+  if (threadIdx.x < p.b) p.d[threadIdx.x] = sm.dsign[threadIdx.x];
+}
+
 // The leaves leaf0 .. leaf0 + lpw - 1 of panel p and the part of its tree
-// this workgroup ends up holding (levels 1-3).
-template <class T, int RPT, int NQ>
+// this workgroup ends up holding (levels 1-3).  Without DEVICE_TREE the
+// workgroup stops where its subtree needs another workgroup's, and the
+// levels above are eliminated by later launches (one per level).
+template <class T, int RPT, int NQ, bool DEVICE_TREE>
 __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
   __shared__ PanelSmem<T> sm;
   constexpr int NCH = (RPT > 2 * NQ) ? RPT : 2 * NQ;
@@ -355,53 +382,57 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
           go_on = false;
           break;
         }
-        if (!arrive(p, partner, sm)) return;         // the sibling's workgroup finishes the node
+        if (!DEVICE_TREE || !arrive(p, partner, sm)) return;  // another workgroup finishes the node
         combine<T, NCH, NQ>(a, p, rt, partner, H, sm);
       } else {  // right child: node id rt, left sibling rt - half
         const int left = rt - half;
         if (left < leaf0) {
-          if (!arrive(p, rt, sm)) return;
+          if (!DEVICE_TREE || !arrive(p, rt, sm)) return;
         }
         combine<T, NCH, NQ>(a, p, left, rt, H, sm);
         rt = left;
       }
     }
     if (!go_on) continue;
-    // ---- root: make the diagonal non-negative, R <- D R, record D
-    __syncthreads();
-    load_r<T, NCH, NQ>(a, p, 0, 0);
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      const int row = 16 * i + r;
-      if (c == r && row < p.b) sm.dsign[row] = (a[i][i] < T(0)) ? T(-1) : T(1);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NQ; ++i)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int row = 16 * i + r, col = c + 16 * q;
-        if (row <= col && col < p.b) a[i][q] *= sm.dsign[row];
-      }
-    store_upper<T, NCH, NQ>(a, p, 0, 0);
-    if (threadIdx.x < p.b) p.d[threadIdx.x] = sm.dsign[threadIdx.x];
+    finish_root<T, NCH, NQ>(a, p, sm);
   }
 }
 
 
 template <int RPT, int NQ>
 __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) {
-  panel_body<double, RPT, NQ>(p, blockIdx.x * p.lpw);
+  panel_body<double, RPT, NQ, true>(p, blockIdx.x * p.lpw);
 }
 
 // Many independent panels in one launch: workgroup i takes problem
-// items[i].x, leaves from items[i].y on (each problem with its own tickets).
+// items[i].x, leaves from items[i].y on, and the tree levels inside its own
+// leaves.  No workgroup waits for or signals another: the levels above are
+// eliminated by tsqr_tree_level_kernel launches, whose kernel boundaries
+// order them (many thousands of workgroups would otherwise each pay an
+// agent-scope fence, an L2 write-back, while the L2s hold the others' data).
 template <class T, int RPT, int NQ>
 __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_batched_kernel(const PanelParamsT<T> *probs,
                                                                         const int2 *items) {
   const int2 it = items[blockIdx.x];
   const PanelParamsT<T> p = probs[__builtin_amdgcn_readfirstlane(it.x)];
-  panel_body<T, RPT, NQ>(p, __builtin_amdgcn_readfirstlane(it.y));
+  panel_body<T, RPT, NQ, false>(p, __builtin_amdgcn_readfirstlane(it.y));
+}
+
+// One device level of the trees of many panels: workgroup i eliminates the
+// R at slot nodes[i].z against the R at slot nodes[i].y of problem
+// nodes[i].x (leaf height nodes[i].w & 0xFFFF), and normalizes the root when
+// the node is the top of its tree (nodes[i].w >> 16).
+template <class T, int NQ>
+__global__ void __launch_bounds__(kThreads, 2) tsqr_tree_level_kernel(const PanelParamsT<T> *probs,
+                                                                     const int4 *nodes) {
+  __shared__ PanelSmem<T> sm;
+  const int4 nd = nodes[blockIdx.x];
+  const PanelParamsT<T> p = probs[__builtin_amdgcn_readfirstlane(nd.x)];
+  const int w = __builtin_amdgcn_readfirstlane(nd.w);
+  T a[2 * NQ][NQ];
+  combine<T, 2 * NQ, NQ>(a, p, __builtin_amdgcn_readfirstlane(nd.y), __builtin_amdgcn_readfirstlane(nd.z),
+                         w & 0xFFFF, sm);
+  if (w >> 16) finish_root<T, 2 * NQ, NQ>(a, p, sm);
 }
 
 template <int RPT, int NQ>
@@ -439,6 +470,24 @@ hipError_t launch_batched_nq(int nq, const PanelParamsT<T> *probs, const int2 *i
   }
 }
 
+template <class T, int NQ>
+hipError_t launch_level_t(const PanelParamsT<T> *probs, const int4 *nodes, int nnodes, hipStream_t s) {
+  hipLaunchKernelGGL((tsqr_tree_level_kernel<T, NQ>), dim3(nnodes), dim3(kThreads), 0, s, probs, nodes);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_level(const PanelParamsT<T> *probs, const int4 *nodes, int nnodes, int nq, hipStream_t s) {
+  if (nnodes < 1) return hipErrorInvalidValue;
+  switch (nq) {
+    case 1: return launch_level_t<T, 1>(probs, nodes, nnodes, s);
+    case 2: return launch_level_t<T, 2>(probs, nodes, nnodes, s);
+    case 3: return launch_level_t<T, 3>(probs, nodes, nnodes, s);
+    case 4: return launch_level_t<T, 4>(probs, nodes, nnodes, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <class T>
 hipError_t launch_batched(const PanelParamsT<T> *probs, const int2 *items, int nitems, int leaf_rows, int nq,
                           hipStream_t s) {
@@ -461,6 +510,14 @@ hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items
 hipError_t launch_tsqr_panel_batched(const PanelParams32 *probs, const int2 *items, int nitems, int leaf_rows, int nq,
                                      hipStream_t s) {
   return launch_batched<float>(probs, items, nitems, leaf_rows, nq, s);
+}
+
+hipError_t launch_tsqr_tree_level(const PanelParams *probs, const int4 *nodes, int nnodes, int nq, hipStream_t s) {
+  return launch_level<double>(probs, nodes, nnodes, nq, s);
+}
+
+hipError_t launch_tsqr_tree_level(const PanelParams32 *probs, const int4 *nodes, int nnodes, int nq, hipStream_t s) {
+  return launch_level<float>(probs, nodes, nnodes, nq, s);
 }
 
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s) {
