@@ -71,7 +71,11 @@ typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
  *   leaf_rows      rows per leaf block: 64, 128 or 256 (default 256).
  *   leaves_per_wg  leaves one workgroup factors and combines in its own
  *                  registers/LDS before the device-wide tree: 1, 2 or 4
- *                  (default 4 for tsqr_factor, 1 for caqr_factor panels).
+ *                  (default 1 for caqr_factor panels and for tsqr_factor
+ *                  with 128 leaves or more, else 4).  A single panel
+ *                  with 128 or more workgroups finishes the device-wide
+ *                  tree with one launch per level instead of workgroups
+ *                  signalling each other.
  * The tree is always the binary tree over leaves that pairs leaf i with leaf
  * i + 2^(k-1) at level k (i a multiple of 2^k), the lower index on top;
  * leaves_per_wg only decides which levels run inside a workgroup, so R, Y, V

@@ -363,12 +363,22 @@ caqr_status_t launch_panel_t(caqr_handle_t h, caqr_factors_t F, int idx, hipStre
 
 // Factor panel idx (the tree climb), then, when asked, form its T factors on
 // the same stream.
+// Workgroups from which a single-panel factorization finishes its tree with
+// one launch per level instead of ticket climbs: with thousands of
+// workgroups, each climb's agent-scope fence (an L2 write-back while the
+// other workgroups fill the L2) costs more than a kernel boundary per level.
+constexpr int kLevelLaunchWgs = 128;
+
 caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form_t, hipStream_t st) {
   const PanelRec &p = F->panels[idx];
   PanelParams pp = panel_params(h, F, p);
+  const bool levels = F->panels.size() == 1 && ceil_div(p.L, F->lpw) >= kLevelLaunchWgs;
   {
     TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
-    if (launch_tsqr_panel(pp, F->leaf_rows, st) != hipSuccess) return CAQR_ERR_DEVICE;
+    if (levels) pp.tickets = nullptr;
+    if (launch_tsqr_panel(pp, F->leaf_rows, st, !levels) != hipSuccess) return CAQR_ERR_DEVICE;
+    for (int half = F->lpw; levels && half < p.L; half *= 2)
+      if (launch_tsqr_level(pp, half, F->leaf_rows, st) != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return form_t ? launch_panel_t(h, F, idx, st) : CAQR_SUCCESS;
 }
@@ -472,7 +482,11 @@ caqr_status_t check_opts(const caqr_tree_opts_t *o) {
 caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
                           const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr, void *ws = nullptr) {
   const int hr = resolve_leaf_rows(opts);
-  const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : (tsqr ? 4 : 1);
+  // default: one leaf per workgroup for CAQR panels and for a single panel
+  // tall enough to finish its tree by level launches; four for shorter
+  // single panels, whose tree climbs take fewer ticket fences that way
+  const bool tall = ceil_div(m, hr) >= kLevelLaunchWgs;
+  const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : ((tsqr && !tall) ? 4 : 1);
   DeviceGuard g(h->device);
   caqr_factors_t f = nullptr;
   caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, ws, &f);

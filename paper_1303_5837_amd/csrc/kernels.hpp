@@ -52,7 +52,13 @@ struct UpdateParams {
                       // whole tree in one launch
 };
 
-hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s);
+// Leaves and tree of one panel.  With device_tree (tickets required), the
+// workgroups climb the whole tree; without, each stops at its own subtree
+// and launch_tsqr_level finishes the tree, one launch per level.
+hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s, bool device_tree = true);
+// Level `half` (pairs (left, left + half), left a multiple of 2 half) of one
+// panel's tree; the top level also normalizes the root.
+hipError_t launch_tsqr_level(const PanelParams &p, int half, int leaf_rows, hipStream_t s);
 
 // Independent panels of equal ceil(b/16) = nq and leaf height in one launch:
 // probs (device) holds one PanelParams per problem, items (device) one

@@ -399,9 +399,21 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
 }
 
 
-template <int RPT, int NQ>
+template <int RPT, int NQ, bool DEVICE_TREE>
 __global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) {
-  panel_body<double, RPT, NQ, true>(p, blockIdx.x * p.lpw);
+  panel_body<double, RPT, NQ, DEVICE_TREE>(p, blockIdx.x * p.lpw);
+}
+
+// One device level of a single panel's tree (when the leaves' launch stops
+// at the workgroups' subtrees): workgroup i eliminates slot left + half
+// against slot left = 2 half i, and normalizes the root at the top level.
+template <int NQ>
+__global__ void __launch_bounds__(kThreads, 2) tsqr_level_kernel(PanelParams p, int half, int h) {
+  __shared__ PanelSmem<double> sm;
+  double a[2 * NQ][NQ];
+  const int left = 2 * half * (int)blockIdx.x;
+  combine<double, 2 * NQ, NQ>(a, p, left, left + half, h, sm);
+  if (2 * half >= p.L) finish_root<double, 2 * NQ, NQ>(a, p, sm);
 }
 
 // Many independent panels in one launch: workgroup i takes problem
@@ -436,21 +448,31 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_tree_level_kernel(const Pane
 }
 
 template <int RPT, int NQ>
-hipError_t launch_panel_t(const PanelParams &p, hipStream_t s) {
+hipError_t launch_panel_t(const PanelParams &p, bool device_tree, hipStream_t s) {
   const int grid = (p.L + p.lpw - 1) / p.lpw;
-  hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ>), dim3(grid), dim3(kThreads), 0, s, p);
+  if (device_tree)
+    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ, true>), dim3(grid), dim3(kThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ, false>), dim3(grid), dim3(kThreads), 0, s, p);
   return hipGetLastError();
 }
 
 template <int RPT>
-hipError_t launch_panel_nq(const PanelParams &p, hipStream_t s) {
+hipError_t launch_panel_nq(const PanelParams &p, bool device_tree, hipStream_t s) {
   switch ((p.b + 15) / 16) {
-    case 1: return launch_panel_t<RPT, 1>(p, s);
-    case 2: return launch_panel_t<RPT, 2>(p, s);
-    case 3: return launch_panel_t<RPT, 3>(p, s);
-    case 4: return launch_panel_t<RPT, 4>(p, s);
+    case 1: return launch_panel_t<RPT, 1>(p, device_tree, s);
+    case 2: return launch_panel_t<RPT, 2>(p, device_tree, s);
+    case 3: return launch_panel_t<RPT, 3>(p, device_tree, s);
+    case 4: return launch_panel_t<RPT, 4>(p, device_tree, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int NQ>
+hipError_t launch_level_single_t(const PanelParams &p, int half, int h, hipStream_t s) {
+  const int nodes = (p.L - half + 2 * half - 1) / (2 * half);
+  hipLaunchKernelGGL((tsqr_level_kernel<NQ>), dim3(nodes), dim3(kThreads), 0, s, p, half, h);
+  return hipGetLastError();
 }
 
 template <class T, int RPT, int NQ>
@@ -520,12 +542,24 @@ hipError_t launch_tsqr_tree_level(const PanelParams32 *probs, const int4 *nodes,
   return launch_level<float>(probs, nodes, nnodes, nq, s);
 }
 
-hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s) {
+hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s, bool device_tree) {
   if (p.b < 1 || p.b > kMaxB || p.L < 1 || p.lpw < 1) return hipErrorInvalidValue;
+  if (device_tree && !p.tickets) return hipErrorInvalidValue;
   switch (leaf_rows) {
-    case 64: return launch_panel_nq<4>(p, s);
-    case 128: return launch_panel_nq<8>(p, s);
-    case 256: return launch_panel_nq<16>(p, s);
+    case 64: return launch_panel_nq<4>(p, device_tree, s);
+    case 128: return launch_panel_nq<8>(p, device_tree, s);
+    case 256: return launch_panel_nq<16>(p, device_tree, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tsqr_level(const PanelParams &p, int half, int leaf_rows, hipStream_t s) {
+  if (p.b < 1 || p.b > kMaxB || half < 1 || half >= p.L) return hipErrorInvalidValue;
+  switch ((p.b + 15) / 16) {
+    case 1: return launch_level_single_t<1>(p, half, leaf_rows, s);
+    case 2: return launch_level_single_t<2>(p, half, leaf_rows, s);
+    case 3: return launch_level_single_t<3>(p, half, leaf_rows, s);
+    case 4: return launch_level_single_t<4>(p, half, leaf_rows, s);
     default: return hipErrorInvalidValue;
   }
 }
