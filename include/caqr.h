@@ -71,11 +71,10 @@ typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
  *   leaf_rows      rows per leaf block: 64, 128 or 256 (default 256).
  *   leaves_per_wg  leaves one workgroup factors and combines in its own
  *                  registers/LDS before the device-wide tree: 1, 2 or 4
- *                  (default 1 for caqr_factor panels and for tsqr_factor
- *                  with 128 leaves or more, else 4).  A single panel
- *                  with 128 or more workgroups finishes the device-wide
- *                  tree with one launch per level instead of workgroups
- *                  signalling each other.
+ *                  (default 1).  A single panel with 128 or more
+ *                  workgroups finishes the device-wide tree with one
+ *                  launch per level instead of workgroups signalling each
+ *                  other.
  * The tree is always the binary tree over leaves that pairs leaf i with leaf
  * i + 2^(k-1) at level k (i a multiple of 2^k), the lower index on top;
  * leaves_per_wg only decides which levels run inside a workgroup, so R, Y, V
@@ -199,7 +198,9 @@ typedef enum {
   CAQR_TRACE_UPDATE_T = 1,  /* Q^T applied to a block of columns (trailing update) */
   CAQR_TRACE_UPDATE_N = 2,  /* Q applied to a block of columns */
   CAQR_TRACE_FORM_T = 3,    /* T factors formed after a factorization without them */
-  CAQR_TRACE_OTHER = 4      /* least-squares helpers */
+  CAQR_TRACE_OTHER = 4,     /* least-squares helpers */
+  CAQR_TRACE_UPDATE_T_LEVELS = 5  /* trailing update of a factorization run as a leaf launch plus one
+                                     launch per tree level (the columns beyond the next panel) */
 } caqr_trace_kind_t;
 
 typedef struct {
@@ -212,8 +213,15 @@ typedef struct {
   double ms;       /* device time of the launch, milliseconds */
 } caqr_trace_entry_t;
 
-/* Enable (1) or disable (0) tracing; either call clears recorded entries. */
+/* Enable (1) or disable (0) tracing of every kind; either call clears
+ * recorded entries. */
 caqr_status_t caqr_set_trace(caqr_handle_t h, int enable);
+
+/* Trace only the kinds whose bit (1 << caqr_trace_kind_t) is set in mask
+ * (0 disables tracing), so that a measurement brackets only the launches it
+ * needs; clears recorded entries.  Errors: CAQR_ERR_INVALID_VALUE for a NULL
+ * handle or bits above CAQR_TRACE_UPDATE_T_LEVELS. */
+caqr_status_t caqr_set_trace_kinds(caqr_handle_t h, uint32_t mask);
 
 /* Wait for the handle's stream and copy up to max entries (in launch order) to
  * host memory; *count receives the number recorded (may exceed max).  Entries

@@ -56,7 +56,7 @@ class TraceEntry(ctypes.Structure):
                 ("ms", ctypes.c_double)]
 
 
-TRACE_KINDS = {0: "panel", 1: "update_t", 2: "update_n", 3: "form_t", 4: "other"}
+TRACE_KINDS = {0: "panel", 1: "update_t", 2: "update_n", 3: "form_t", 4: "other", 5: "update_t_levels"}
 
 
 class LsOpts(ctypes.Structure):
@@ -82,7 +82,7 @@ _lib_lock = threading.Lock()
 EXPORTS = [
     "caqr_create", "caqr_destroy", "caqr_set_stream", "caqr_get_stream", "caqr_set_workspace_limit", "caqr_sync",
     "caqr_status_string", "caqr_device_count", "tsqr_factor", "caqr_factor", "apply_q", "caqr_factors_destroy",
-    "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_trace_read",
+    "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_set_trace_kinds", "caqr_trace_read",
     "tsqr_factor_batched", "caqr_batch_destroy", "caqr_batch_get_plan", "caqr_batch_get_signs", "caqr_tune_batched",
     "caqr_batch_plan_for", "caqr_server_create", "caqr_server_submit", "caqr_server_wait", "caqr_server_destroy",
 ]
@@ -114,6 +114,7 @@ def _lib():
         L.caqr_factors_get_signs.argtypes = [vp, vp, dp]
         L.ls_solve.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(LsOpts), ctypes.POINTER(LsInfo)]
         L.caqr_set_trace.argtypes = [vp, i32]
+        L.caqr_set_trace_kinds.argtypes = [vp, ctypes.c_uint32]
         L.caqr_trace_read.argtypes = [vp, ctypes.POINTER(TraceEntry), i64, ctypes.POINTER(i64)]
         pi64 = ctypes.POINTER(i64)
         L.tsqr_factor_batched.argtypes = [vp, i64, pi64, pi64, ctypes.POINTER(vp), pi64, i32,
@@ -172,6 +173,14 @@ class Handle:
 
     def set_trace(self, enable: bool):
         _check(_lib().caqr_set_trace(self._h, 1 if enable else 0), "caqr_set_trace")
+
+    def set_trace_kinds(self, kinds):
+        """Trace only the named kinds ("panel", "update_t", "update_n", "form_t", "other")."""
+        mask = 0
+        codes = {v: k for k, v in TRACE_KINDS.items()}
+        for k in kinds:
+            mask |= 1 << codes[k]
+        _check(_lib().caqr_set_trace_kinds(self._h, mask), "caqr_set_trace_kinds")
 
     def take_trace(self, max_entries: int = 1 << 16):
         """Recorded launches (launch order) with their device time in ms; clears the record."""

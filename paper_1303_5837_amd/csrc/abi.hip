@@ -65,6 +65,7 @@ struct caqr_handle_s {
   size_t tickets_cap = 0;          // counters
   int64_t *status_dev = nullptr;   // 2 words for ls_solve
   bool trace = false;
+  uint32_t trace_mask = 0;            // kinds traced (bit 1 << caqr_trace_kind_t)
   std::vector<TraceRec> trace_recs;   // recorded launches
   std::vector<hipEvent_t> event_pool; // free events
   hipStream_t side = nullptr;         // look-ahead stream (default priority, created on first use)
@@ -144,7 +145,7 @@ struct TraceScope {
   bool on;
   TraceScope(caqr_handle_t hh, int kind, int panel, int64_t rows, int64_t cols, int width, int leaves,
              hipStream_t st = nullptr)
-      : h(hh), stream(st ? st : hh->stream), on(hh->trace) {
+      : h(hh), stream(st ? st : hh->stream), on(hh->trace && ((hh->trace_mask >> kind) & 1u)) {
     if (!on) return;
     rec.e.kind = kind;
     rec.e.panel = panel;
@@ -389,7 +390,9 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
   UpdateParams u = update_params(h, F, p, F->A + c0 * F->lda, F->lda, k);
   // the tickets belong to the handle's stream (panel kernels use them too)
   if (st == h->stream) u.tickets = panel_tickets(h);
-  TraceScope ts(h, CAQR_TRACE_UPDATE_T, idx, p.m, k, p.b, p.L, st);
+  // the same test launch_apply_qt makes: one tree-climbing launch, or levels
+  const bool one_launch = u.tickets && u.tiles <= kTreeTiles && u.L > 1;
+  TraceScope ts(h, one_launch ? CAQR_TRACE_UPDATE_T : CAQR_TRACE_UPDATE_T_LEVELS, idx, p.m, k, p.b, p.L, st);
   return launch_apply_qt(u, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
 }
 
@@ -482,11 +485,8 @@ caqr_status_t check_opts(const caqr_tree_opts_t *o) {
 caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
                           const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr, void *ws = nullptr) {
   const int hr = resolve_leaf_rows(opts);
-  // default: one leaf per workgroup for CAQR panels and for a single panel
-  // tall enough to finish its tree by level launches; four for shorter
-  // single panels, whose tree climbs take fewer ticket fences that way
-  const bool tall = ceil_div(m, hr) >= kLevelLaunchWgs;
-  const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : ((tsqr && !tall) ? 4 : 1);
+  // default: one leaf per workgroup (every leaf factored in parallel)
+  const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : 1;
   DeviceGuard g(h->device);
   caqr_factors_t f = nullptr;
   caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, ws, &f);
@@ -778,6 +778,17 @@ caqr_status_t caqr_set_trace(caqr_handle_t h, int enable) {
   if (hipStreamSynchronize(h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
   trace_clear(h);
   h->trace = enable != 0;
+  h->trace_mask = enable ? 0x3Fu : 0u;
+  return CAQR_SUCCESS;
+}
+
+caqr_status_t caqr_set_trace_kinds(caqr_handle_t h, uint32_t mask) {
+  if (!h || (mask >> (CAQR_TRACE_UPDATE_T_LEVELS + 1))) return CAQR_ERR_INVALID_VALUE;
+  DeviceGuard g(h->device);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+  trace_clear(h);
+  h->trace = mask != 0;
+  h->trace_mask = mask;
   return CAQR_SUCCESS;
 }
 

@@ -152,7 +152,8 @@ def test_f32_full_uneven_batch():
     sample = sorted(set(order[:: len(order) // 8].tolist() + [int(order[-1]), int(order[0])]))
     host = {i: As[i].cpu().numpy().astype(np.float64) for i in sample}
     banner(f"f32 full batch: {len(As)} problems")
-    B = caqr.tsqr_batched(As, leaf_rows=256, leaves_per_wg=4)
+    caqr.tune_batched(dtype=torch.float32)
+    B = caqr.tsqr_batched(As)
     torch.cuda.synchronize()
     worst = 0.0
     for a, g in zip(As, grams):

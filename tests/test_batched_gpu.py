@@ -101,7 +101,8 @@ def test_full_uneven_batch_sampled():
     sample = sorted(set(order[:: len(order) // 10].tolist() + [int(order[-1]), int(order[0])]))
     host = {i: As[i].cpu().numpy() for i in sample}
     banner(f"full batch: {len(As)} problems, {sum(int(m) * int(n) for m, n in zip(ms, ns)) * 8 / 2**30:.2f} GiB")
-    B = caqr.tsqr_batched(As, leaf_rows=256, leaves_per_wg=4)
+    caqr.tune_batched()
+    B = caqr.tsqr_batched(As)
     torch.cuda.synchronize()
     worst = 0.0
     for i, (a, g) in enumerate(zip(As, grams)):

@@ -31,6 +31,7 @@ CASES = [
     (5000, 1, 256, 0),
     (1, 1, 256, 0),
     (40000, 17, 256, 4),  # 157 leaves, several device levels
+    (40000, 17, 256, 1),  # 157 workgroups: tree finished by one launch per level
     (33000, 64, 128, 2),
 ]
 
@@ -82,14 +83,17 @@ def test_config0_invariants_and_apply_q():
 
 
 def test_grouping_does_not_change_anything():
-    """leaves_per_wg only moves tree levels between a workgroup and the device: bitwise equal."""
+    """leaves_per_wg only moves tree levels between a workgroup and the device: bitwise equal.
+    At 40000 rows (313 leaves of 128) one and two leaves per workgroup finish the tree by one
+    launch per level, four by ticket climbs: the two device-level schemes agree bitwise too."""
     require_gpu()
-    A = inputs.gaussian(9000, 40, 77)
-    outs = []
-    for lpw in (1, 2, 4):
-        F, R = tsqr_gpu(A, leaf_rows=128, leaves_per_wg=lpw)
-        outs.append(factored(F))
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for m, seed in ((9000, 77), (40000, 76)):
+        A = inputs.gaussian(m, 40, seed)
+        outs = []
+        for lpw in (1, 2, 4):
+            F, R = tsqr_gpu(A, leaf_rows=128, leaves_per_wg=lpw)
+            outs.append(factored(F))
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2]), m
 
 
 def test_leaf_height_independence():
