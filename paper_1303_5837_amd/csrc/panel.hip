@@ -37,6 +37,18 @@ namespace caqr {
 
 namespace {
 
+// Waves per panel workgroup.  A workgroup of W wave64s holds a block with
+// thread t (wave w = t / 64, lane l = t % 64) owning the elements
+//     (row 16 i + l % 16, column c + 4 W s),  c = 4 w + l / 16 = 0 .. 4W - 1,
+// for chunk i and column slot s: every column lives in the 16 lanes of one
+// DPP row, which hold all its rows, so a column reduction is the same 4-step
+// butterfly over the same partial sums whatever W is, and the results do not
+// depend on W.  Four waves: eight halve each thread's column slots (and the
+// dot products, reductions and updates per step) but were slower on every
+// panel shape measured (an eight-wave barrier per step, and one workgroup per
+// CU instead of two).
+constexpr int kPanelWaves = 4;
+
 template <class T>
 struct PanelSmem {
   T v[2][16 * 16];  // Householder vector of the current step (by row), double-buffered
@@ -55,40 +67,46 @@ template <> struct Lim<float> {
   static constexpr float tiny = FLT_MIN, huge = FLT_MAX;
 };
 
+__device__ __forceinline__ int col_group() { return (threadIdx.x >> 6) * 4 + ((threadIdx.x & 63) >> 4); }
+
 // One Householder step per column j = 0..b-1 on the block held in a[][]:
 // NACT chunk rows of 16 (LEAF: rows 0..16*NACT-1 of a dense block; STACK: two
-// stacked upper triangles, R_top in chunks 0..NQ-1 and R_bot in chunks
-// NQ..2NQ-1).  Reflector convention: beta = -sign(alpha) ||x||,
-// tau = (beta - alpha) / beta, v = [1; x(2:) / (alpha - beta)]; x(2:) == 0 gives
-// tau = 0 (H = I).  The norm is an unscaled sum of squares, recomputed with
-// power-of-two scaling when alpha^2 + sigma is zero, subnormal or overflows.
-// T is double, or float for the single-precision batched TSQR (same steps).
-template <class T, int NCH, int NQ, int NACT, bool STACK>
-__device__ __forceinline__ void householder_steps(T (&a)[NCH][NQ], int b, PanelSmem<T> &sm) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int r = lane & 15;
-  const int c = (tid >> 6) * 4 + (lane >> 4);
+// stacked upper triangles, R_top in chunks 0..NB-1 and R_bot in chunks
+// NB..2NB-1, NB = ceil(b/16)).  Column j has its diagonal in chunk D = j/16 and
+// lives in slot S = j / 4W of column group c = j mod 4W.  Reflector convention:
+// beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
+// v = [1; x(2:) / (alpha - beta)]; x(2:) == 0 gives tau = 0 (H = I).  The norm
+// is an unscaled sum of squares, recomputed with power-of-two scaling when
+// alpha^2 + sigma is zero, subnormal or overflows.  T is double, or float for
+// the single-precision batched TSQR (same steps).
+template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK>
+__device__ __forceinline__ void householder_steps(T (&a)[NCH][NS], int b, PanelSmem<T> &sm) {
+  constexpr int CPS = 4 * W;    // columns per slot
+  constexpr int BPS = CPS / 16;  // diagonal blocks per slot
+  const int r = threadIdx.x & 15;
+  const int c = col_group();
 #pragma unroll
-  for (int Q = 0; Q < NQ; ++Q) {
-    for (int cj = 0; cj < 16; ++cj) {
-      const int j = 16 * Q + cj;
+  for (int D = 0; D < NB; ++D) {
+    const int S = D / BPS;
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * D + jj;
       if (j >= b) break;
+      const int cj = 16 * (D % BPS) + jj;  // column group of column j
       const int par = j & 1;
       if (c == cj) {
-        // ---- owner DPP row: reflector of column j (slot Q of this thread)
+        // ---- owner DPP row: reflector of column j (slot S of this thread)
         // sum of squares below the diagonal: four partial sums (short chain)
         T sp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int i = 0; i < NACT; ++i) {
-          const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
+          const bool act = STACK ? (i == D || (i >= NB && i <= NB + D)) : (i >= D);
           if (!act) continue;
-          const bool below = (i > Q) || (r > cj);
-          const T e = a[i][Q];
+          const bool below = (i > D) || (r > jj);
+          const T e = a[i][S];
           sp[i & 3] = below ? fma(e, e, sp[i & 3]) : sp[i & 3];
         }
         T sig = row16_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
-        const T alpha = readlane_t(a[Q][Q], (cj & 3) * 16 + cj);
+        const T alpha = readlane_t(a[D][S], (cj & 3) * 16 + jj);
         const T s2 = fma(alpha, alpha, sig);
         // The reflector is formed from x scaled by 2^sh: sh = 0 normally; when
         // alpha^2 + sigma is zero, subnormal, overflowing or NaN, sh = -ilogb(max|x|)
@@ -102,10 +120,10 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NQ], int b, PanelS
           T mx = T(0);
 #pragma unroll
           for (int i = 0; i < NACT; ++i) {
-            const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
+            const bool act = STACK ? (i == D || (i >= NB && i <= NB + D)) : (i >= D);
             if (!act) continue;
-            const bool inx = (i > Q) || (r >= cj);
-            mx = inx ? fmax(mx, fabs(a[i][Q])) : mx;
+            const bool inx = (i > D) || (r >= jj);
+            mx = inx ? fmax(mx, fabs(a[i][S])) : mx;
           }
           mx = row16_max(mx);
           if (mx == T(0) || !(mx <= Lim<T>::huge)) {  // zero column, or Inf/NaN (propagated)
@@ -118,10 +136,10 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NQ], int b, PanelS
             T ss[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int i = 0; i < NACT; ++i) {
-              const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
+              const bool act = STACK ? (i == D || (i >= NB && i <= NB + D)) : (i >= D);
               if (!act) continue;
-              const bool below = (i > Q) || (r > cj);
-              const T e = ldexp(a[i][Q], sh);
+              const bool below = (i > D) || (r > jj);
+              const T e = ldexp(a[i][S], sh);
               ss[i & 3] = below ? fma(e, e, ss[i & 3]) : ss[i & 3];
             }
             sig_s = row16_sum((ss[0] + ss[1]) + (ss[2] + ss[3]));
@@ -138,22 +156,22 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NQ], int b, PanelS
           const T beta_s = -copysign(mu_s, alpha_s);
           tau = (beta_s - alpha_s) / beta_s;
           // |alpha - beta| = |alpha| + mu lies in [mu, 2 mu], a normal number:
-          // its reciprocal from the hardware estimate refined by two Newton
-          // steps, independent of the division above so that the two overlap
+          // its reciprocal from the hardware estimate refined by Newton steps,
+          // independent of the division above so that the two overlap
           scal = rcp_nr(alpha_s - beta_s);
           beta = ldexp(beta_s, -sh);
         }
 #pragma unroll
         for (int i = 0; i < NACT; ++i) {
-          const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
+          const bool act = STACK ? (i == D || (i >= NB && i <= NB + D)) : (i >= D);
           if (!act) continue;
           T vv;
-          if (i > Q || r > cj) {
-            vv = (sh == 0 ? a[i][Q] : ldexp(a[i][Q], sh)) * scal;
-            a[i][Q] = vv;
-          } else if (r == cj && i == Q) {
+          if (i > D || r > jj) {
+            vv = (sh == 0 ? a[i][S] : ldexp(a[i][S], sh)) * scal;
+            a[i][S] = vv;
+          } else if (r == jj && i == D) {
             vv = T(1);
-            a[i][Q] = beta;
+            a[i][S] = beta;
           } else {
             vv = T(0);
           }
@@ -167,39 +185,39 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NQ], int b, PanelS
       __syncthreads();
       // ---- every thread: w = v^T A(:, col) for its column slots, then the rank-1 update.
       // v is read from LDS where it is used (not held across the reductions).
-      // Slots whose columns are all finished (q < Q) are skipped.
+      // Slots whose columns are all finished (q < S) are skipped.
       const T tau = sm.tau[par];
       const T *vrow = sm.v[par] + r;
-      T p[2][NQ];  // two partial sums per slot (half the dependency chain)
+      T p[2][NS];  // two partial sums per slot (half the dependency chain)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) p[0][q] = p[1][q] = T(0);
+      for (int q = 0; q < NS; ++q) p[0][q] = p[1][q] = T(0);
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
-        const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
+        const bool act = STACK ? (i == D || (i >= NB && i <= NB + D)) : (i >= D);
         if (!act) continue;
         const T vi = vrow[16 * i];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          if (q < Q) continue;
+        for (int q = 0; q < NS; ++q) {
+          if (q < S) continue;
           p[i & 1][q] = fma(vi, a[i][q], p[i & 1][q]);
         }
       }
-      T coef[NQ];
+      T coef[NS];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if (q < Q) continue;
+      for (int q = 0; q < NS; ++q) {
+        if (q < S) continue;
         const T w = row16_sum(p[0][q] + p[1][q]);
-        const int col = c + 16 * q;
+        const int col = c + CPS * q;
         coef[q] = (col > j && col < b) ? tau * w : T(0);
       }
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
-        const bool act = STACK ? (i == Q || (i >= NQ && i <= NQ + Q)) : (i >= Q);
+        const bool act = STACK ? (i == D || (i >= NB && i <= NB + D)) : (i >= D);
         if (!act) continue;
         const T vi = vrow[16 * i];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          if (q < Q) continue;  // finished columns are never updated
+        for (int q = 0; q < NS; ++q) {
+          if (q < S) continue;  // finished columns are never updated
           a[i][q] = fma(-coef[q], vi, a[i][q]);
         }
       }
@@ -213,59 +231,56 @@ __device__ __forceinline__ T *pan(const PanelParamsT<T> &p, int64_t row, int col
   return p.A + row + (int64_t)col * p.lda;
 }
 
-// Load the upper triangle of the R stored at slot `leaf` into chunks
-// base..base+NQ-1 (zeros elsewhere).
-template <class T, int NCH, int NQ>
-__device__ __forceinline__ void load_r(T (&a)[NCH][NQ], const PanelParamsT<T> &p, int64_t slot_row, int base) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15;
-  const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
+// Load the upper triangle of the R stored at slot_row into chunks
+// base..base+NB-1 (zeros elsewhere).
+template <class T, int W, int NCH, int NB, int NS>
+__device__ __forceinline__ void load_r(T (&a)[NCH][NS], const PanelParamsT<T> &p, int64_t slot_row, int base) {
+  const int r = threadIdx.x & 15;
+  const int c = col_group();
 #pragma unroll
-  for (int i = 0; i < NQ; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int row = 16 * i + r, col = c + 16 * q;
+    for (int q = 0; q < NS; ++q) {
+      const int row = 16 * i + r, col = c + 4 * W * q;
       const int64_t grow = slot_row + row;
       a[base + i][q] = (row <= col && col < p.b && grow < p.m) ? *pan(p, grow, col) : T(0);
     }
 }
 
-// Store the upper triangle (incl. diagonal) held in chunks base..base+NQ-1 to
+// Store the upper triangle (incl. diagonal) held in chunks base..base+NB-1 to
 // the rows starting at slot_row.
-template <class T, int NCH, int NQ>
-__device__ __forceinline__ void store_upper(const T (&a)[NCH][NQ], const PanelParamsT<T> &p, int64_t slot_row,
+template <class T, int W, int NCH, int NB, int NS>
+__device__ __forceinline__ void store_upper(const T (&a)[NCH][NS], const PanelParamsT<T> &p, int64_t slot_row,
                                             int base) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15;
-  const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
+  const int r = threadIdx.x & 15;
+  const int c = col_group();
 #pragma unroll
-  for (int i = 0; i < NQ; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int row = 16 * i + r, col = c + 16 * q;
+    for (int q = 0; q < NS; ++q) {
+      const int row = 16 * i + r, col = c + 4 * W * q;
       const int64_t grow = slot_row + row;
       if (row <= col && col < p.b && grow < p.m) *pan(p, grow, col) = a[base + i][q];
     }
 }
 
 // Eliminate the R at slot `right` against the R at slot `left` (both read from
-// global).  Writes V over the right slot, tau/T of node `right`, and the new
-// R over the left slot.  The new R stays in chunks 0..NQ-1.
-template <class T, int NCH, int NQ>
-__device__ __forceinline__ void combine(T (&a)[NCH][NQ], const PanelParamsT<T> &p, int left, int right, int h,
+// global).  Writes V over the right slot, tau of node `right`, and the new R
+// over the left slot.  The new R stays in chunks 0..NB-1.
+template <class T, int W, int NCH, int NB, int NS>
+__device__ __forceinline__ void combine(T (&a)[NCH][NS], const PanelParamsT<T> &p, int left, int right, int h,
                                         PanelSmem<T> &sm) {
   const int64_t lrow = (int64_t)left * h, rrow = (int64_t)right * h;
-  load_r<T, NCH, NQ>(a, p, lrow, 0);
-  load_r<T, NCH, NQ>(a, p, rrow, NQ);
+  load_r<T, W, NCH, NB, NS>(a, p, lrow, 0);
+  load_r<T, W, NCH, NB, NS>(a, p, rrow, NB);
   __syncthreads();
-  householder_steps<T, NCH, NQ, 2 * NQ, true>(a, p.b, sm);
-  store_upper<T, NCH, NQ>(a, p, rrow, NQ);  // V of the node
-  store_upper<T, NCH, NQ>(a, p, lrow, 0);   // R of the survivor
+  householder_steps<T, W, NCH, NB, NS, 2 * NB, true>(a, p.b, sm);
+  store_upper<T, W, NCH, NB, NS>(a, p, rrow, NB);  // V of the node
+  store_upper<T, W, NCH, NB, NS>(a, p, lrow, 0);   // R of the survivor
   __syncthreads();
   if (threadIdx.x < kMaxB) p.tau_node[(int64_t)right * kMaxB + threadIdx.x] = (threadIdx.x < p.b) ? sm.taus[threadIdx.x] : T(0);
   __syncthreads();
 }
-
 // Last-arriver ticket on node `node`; true when this workgroup arrived second
 // (and must perform the elimination).  Publishes this workgroup's prior global
 // stores before the ticket and acquires the partner's after it.
@@ -284,56 +299,64 @@ __device__ __forceinline__ bool arrive(const PanelParamsT<T> &p, int node, Panel
   return second;
 }
 
+
 // Root of the tree: make the diagonal non-negative, R <- D R, record D.
-template <class T, int NCH, int NQ>
-__device__ __forceinline__ void finish_root(T (&a)[NCH][NQ], const PanelParamsT<T> &p, PanelSmem<T> &sm) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15;
-  const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
+template <class T, int W, int NCH, int NB, int NS>
+__device__ __forceinline__ void finish_root(T (&a)[NCH][NS], const PanelParamsT<T> &p, PanelSmem<T> &sm) {
+  constexpr int BPS = 4 * W / 16;
+  const int r = threadIdx.x & 15;
+  const int c = col_group();
   __syncthreads();
-  load_r<T, NCH, NQ>(a, p, 0, 0);
+  load_r<T, W, NCH, NB, NS>(a, p, 0, 0);
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const int row = 16 * i + r;
-    if (c == r && row < p.b) sm.dsign[row] = (a[i][i] < T(0)) ? T(-1) : T(1);
+  for (int i = 0; i < NB; ++i) {
+    const int row = 16 * i + r;  // its diagonal element: slot i / BPS, column group row mod 4W
+    if (c == 16 * (i % BPS) + r && row < p.b) sm.dsign[row] = (a[i][i / BPS] < T(0)) ? T(-1) : T(1);
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NQ; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int row = 16 * i + r, col = c + 16 * q;
+    for (int q = 0; q < NS; ++q) {
+      const int row = 16 * i + r, col = c + 4 * W * q;
       if (row <= col && col < p.b) a[i][q] *= sm.dsign[row];
     }
-  store_upper<T, NCH, NQ>(a, p, 0, 0);
+  store_upper<T, W, NCH, NB, NS>(a, p, 0, 0);
   if (threadIdx.x < p.b) p.d[threadIdx.x] = sm.dsign[threadIdx.x];
 }
+
+// Column slots of a W-wave workgroup for NB 16-column blocks.
+template <int W, int NB>
+struct Slots {
+  static constexpr int value = (16 * NB + 4 * W - 1) / (4 * W);
+};
 
 // The leaves leaf0 .. leaf0 + lpw - 1 of panel p and the part of its tree
 // this workgroup ends up holding (levels 1-3).  Without DEVICE_TREE the
 // workgroup stops where its subtree needs another workgroup's, and the
 // levels above are eliminated by later launches (one per level).
-template <class T, int RPT, int NQ, bool DEVICE_TREE>
+template <class T, int W, int RPT, int NB, bool DEVICE_TREE>
 __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
   __shared__ PanelSmem<T> sm;
-  constexpr int NCH = (RPT > 2 * NQ) ? RPT : 2 * NQ;
+  constexpr int NS = Slots<W, NB>::value;
+  constexpr int CPS = 4 * W;
+  constexpr int NCH = (RPT > 2 * NB) ? RPT : 2 * NB;
   constexpr int H = 16 * RPT;
-  T a[NCH][NQ];
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15;
-  const int c = (threadIdx.x >> 6) * 4 + (lane >> 4);
+  T a[NCH][NS];
+  const int r = threadIdx.x & 15;
+  const int c = col_group();
   const int nleaves = min(p.lpw, p.L - leaf0);
 
   for (int li = 0; li < nleaves; ++li) {
     const int leaf = leaf0 + li;
     const int64_t row0 = (int64_t)leaf * H;
     // ---- level 1: factor the leaf block in registers
-    // uniform fast path: the whole leaf in range and the panel 16*NQ wide
-    const bool full = row0 + H <= p.m && p.b == 16 * NQ;
+    // uniform fast path: the whole leaf in range and the panel NS*4W wide
+    const bool full = row0 + H <= p.m && p.b == CPS * NS;
     if (full) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const T *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
+      for (int q = 0; q < NS; ++q) {
+        const T *colp = p.A + row0 + r + (int64_t)(c + CPS * q) * p.lda;
 #pragma unroll
         for (int i = 0; i < NCH; ++i) a[i][q] = (i < RPT) ? colp[16 * i] : T(0);
       }
@@ -341,18 +364,18 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
 #pragma unroll
       for (int i = 0; i < NCH; ++i)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
+        for (int q = 0; q < NS; ++q) {
           const int64_t grow = row0 + 16 * i + r;
-          const int col = c + 16 * q;
+          const int col = c + CPS * q;
           a[i][q] = (i < RPT && grow < p.m && col < p.b) ? *pan(p, grow, col) : T(0);
         }
     }
     __syncthreads();
-    householder_steps<T, NCH, NQ, RPT, false>(a, p.b, sm);
+    householder_steps<T, W, NCH, NB, NS, RPT, false>(a, p.b, sm);
     if (full) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        T *colp = p.A + row0 + r + (int64_t)(c + 16 * q) * p.lda;
+      for (int q = 0; q < NS; ++q) {
+        T *colp = p.A + row0 + r + (int64_t)(c + CPS * q) * p.lda;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) colp[16 * i] = a[i][q];
       }
@@ -360,9 +383,9 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
 #pragma unroll
       for (int i = 0; i < RPT; ++i)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
+        for (int q = 0; q < NS; ++q) {
           const int64_t grow = row0 + 16 * i + r;
-          const int col = c + 16 * q;
+          const int col = c + CPS * q;
           if (grow < p.m && col < p.b) *pan(p, grow, col) = a[i][q];
         }
     }
@@ -383,37 +406,37 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
           break;
         }
         if (!DEVICE_TREE || !arrive(p, partner, sm)) return;  // another workgroup finishes the node
-        combine<T, NCH, NQ>(a, p, rt, partner, H, sm);
+        combine<T, W, NCH, NB, NS>(a, p, rt, partner, H, sm);
       } else {  // right child: node id rt, left sibling rt - half
         const int left = rt - half;
         if (left < leaf0) {
           if (!DEVICE_TREE || !arrive(p, rt, sm)) return;
         }
-        combine<T, NCH, NQ>(a, p, left, rt, H, sm);
+        combine<T, W, NCH, NB, NS>(a, p, left, rt, H, sm);
         rt = left;
       }
     }
     if (!go_on) continue;
-    finish_root<T, NCH, NQ>(a, p, sm);
+    finish_root<T, W, NCH, NB, NS>(a, p, sm);
   }
 }
 
-
-template <int RPT, int NQ, bool DEVICE_TREE>
-__global__ void __launch_bounds__(kThreads, 2) tsqr_panel_kernel(PanelParams p) {
-  panel_body<double, RPT, NQ, DEVICE_TREE>(p, blockIdx.x * p.lpw);
+template <int RPT, int NB, bool DEVICE_TREE>
+__global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_panel_kernel(PanelParams p) {
+  panel_body<double, kPanelWaves, RPT, NB, DEVICE_TREE>(p, blockIdx.x * p.lpw);
 }
 
 // One device level of a single panel's tree (when the leaves' launch stops
 // at the workgroups' subtrees): workgroup i eliminates slot left + half
 // against slot left = 2 half i, and normalizes the root at the top level.
-template <int NQ>
-__global__ void __launch_bounds__(kThreads, 2) tsqr_level_kernel(PanelParams p, int half, int h) {
+template <int NB>
+__global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_level_kernel(PanelParams p, int half, int h) {
+  constexpr int NS = Slots<kPanelWaves, NB>::value;
   __shared__ PanelSmem<double> sm;
-  double a[2 * NQ][NQ];
+  double a[2 * NB][NS];
   const int left = 2 * half * (int)blockIdx.x;
-  combine<double, 2 * NQ, NQ>(a, p, left, left + half, h, sm);
-  if (2 * half >= p.L) finish_root<double, 2 * NQ, NQ>(a, p, sm);
+  combine<double, kPanelWaves, 2 * NB, NB, NS>(a, p, left, left + half, h, sm);
+  if (2 * half >= p.L) finish_root<double, kPanelWaves, 2 * NB, NB, NS>(a, p, sm);
 }
 
 // Many independent panels in one launch: workgroup i takes problem
@@ -422,38 +445,41 @@ __global__ void __launch_bounds__(kThreads, 2) tsqr_level_kernel(PanelParams p, 
 // eliminated by tsqr_tree_level_kernel launches, whose kernel boundaries
 // order them (many thousands of workgroups would otherwise each pay an
 // agent-scope fence, an L2 write-back, while the L2s hold the others' data).
-template <class T, int RPT, int NQ>
-__global__ void __launch_bounds__(kThreads, 2) tsqr_panel_batched_kernel(const PanelParamsT<T> *probs,
-                                                                        const int2 *items) {
+template <class T, int RPT, int NB>
+__global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_panel_batched_kernel(const PanelParamsT<T> *probs,
+                                                                                const int2 *items) {
   const int2 it = items[blockIdx.x];
   const PanelParamsT<T> p = probs[__builtin_amdgcn_readfirstlane(it.x)];
-  panel_body<T, RPT, NQ, false>(p, __builtin_amdgcn_readfirstlane(it.y));
+  panel_body<T, kPanelWaves, RPT, NB, false>(p, __builtin_amdgcn_readfirstlane(it.y));
 }
 
 // One device level of the trees of many panels: workgroup i eliminates the
 // R at slot nodes[i].z against the R at slot nodes[i].y of problem
 // nodes[i].x (leaf height nodes[i].w & 0xFFFF), and normalizes the root when
 // the node is the top of its tree (nodes[i].w >> 16).
-template <class T, int NQ>
-__global__ void __launch_bounds__(kThreads, 2) tsqr_tree_level_kernel(const PanelParamsT<T> *probs,
-                                                                     const int4 *nodes) {
+template <class T, int NB>
+__global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_tree_level_kernel(const PanelParamsT<T> *probs,
+                                                                             const int4 *nodes) {
+  constexpr int NS = Slots<kPanelWaves, NB>::value;
   __shared__ PanelSmem<T> sm;
   const int4 nd = nodes[blockIdx.x];
   const PanelParamsT<T> p = probs[__builtin_amdgcn_readfirstlane(nd.x)];
   const int w = __builtin_amdgcn_readfirstlane(nd.w);
-  T a[2 * NQ][NQ];
-  combine<T, 2 * NQ, NQ>(a, p, __builtin_amdgcn_readfirstlane(nd.y), __builtin_amdgcn_readfirstlane(nd.z),
-                         w & 0xFFFF, sm);
-  if (w >> 16) finish_root<T, 2 * NQ, NQ>(a, p, sm);
+  T a[2 * NB][NS];
+  combine<T, kPanelWaves, 2 * NB, NB, NS>(a, p, __builtin_amdgcn_readfirstlane(nd.y),
+                                          __builtin_amdgcn_readfirstlane(nd.z), w & 0xFFFF, sm);
+  if (w >> 16) finish_root<T, kPanelWaves, 2 * NB, NB, NS>(a, p, sm);
 }
 
-template <int RPT, int NQ>
+constexpr int kPanelThreads = 64 * kPanelWaves;
+
+template <int RPT, int NB>
 hipError_t launch_panel_t(const PanelParams &p, bool device_tree, hipStream_t s) {
   const int grid = (p.L + p.lpw - 1) / p.lpw;
   if (device_tree)
-    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ, true>), dim3(grid), dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NB, true>), dim3(grid), dim3(kPanelThreads), 0, s, p);
   else
-    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NQ, false>), dim3(grid), dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NB, false>), dim3(grid), dim3(kPanelThreads), 0, s, p);
   return hipGetLastError();
 }
 
@@ -468,16 +494,16 @@ hipError_t launch_panel_nq(const PanelParams &p, bool device_tree, hipStream_t s
   }
 }
 
-template <int NQ>
+template <int NB>
 hipError_t launch_level_single_t(const PanelParams &p, int half, int h, hipStream_t s) {
   const int nodes = (p.L - half + 2 * half - 1) / (2 * half);
-  hipLaunchKernelGGL((tsqr_level_kernel<NQ>), dim3(nodes), dim3(kThreads), 0, s, p, half, h);
+  hipLaunchKernelGGL((tsqr_level_kernel<NB>), dim3(nodes), dim3(kPanelThreads), 0, s, p, half, h);
   return hipGetLastError();
 }
 
-template <class T, int RPT, int NQ>
+template <class T, int RPT, int NB>
 hipError_t launch_batched_t(const PanelParamsT<T> *probs, const int2 *items, int nitems, hipStream_t s) {
-  hipLaunchKernelGGL((tsqr_panel_batched_kernel<T, RPT, NQ>), dim3(nitems), dim3(kThreads), 0, s, probs, items);
+  hipLaunchKernelGGL((tsqr_panel_batched_kernel<T, RPT, NB>), dim3(nitems), dim3(kPanelThreads), 0, s, probs, items);
   return hipGetLastError();
 }
 
@@ -492,9 +518,9 @@ hipError_t launch_batched_nq(int nq, const PanelParamsT<T> *probs, const int2 *i
   }
 }
 
-template <class T, int NQ>
+template <class T, int NB>
 hipError_t launch_level_t(const PanelParamsT<T> *probs, const int4 *nodes, int nnodes, hipStream_t s) {
-  hipLaunchKernelGGL((tsqr_tree_level_kernel<T, NQ>), dim3(nnodes), dim3(kThreads), 0, s, probs, nodes);
+  hipLaunchKernelGGL((tsqr_tree_level_kernel<T, NB>), dim3(nnodes), dim3(kPanelThreads), 0, s, probs, nodes);
   return hipGetLastError();
 }
 
