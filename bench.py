@@ -120,6 +120,69 @@ def batched_line(dtype_name: str):
         "timed": "one tsqr_factor_batched call incl. planning and table upload (HIP events)"}
 
 
+def batched_ls_line(reps=5, eta_sample=8):
+    """Batched least squares over the uneven batch's shapes (2000 problems, m
+    log-uniform in [256, 65536], n in {8, 16, 32, 64}, one right-hand side):
+    median of `reps` ls_solve_batched calls (synchronous; planning, factorization,
+    Q^T b and back substitution), against the same problems solved one
+    ls_solve call at a time (once)."""
+    import numpy as np
+    import torch
+
+    from paper_1303_5837_amd import caqr, inputs
+
+    ms, ns = inputs.batched_tsqr_sizes()
+    seed = inputs.SEEDS["batched_tsqr"]
+    P = [inputs.gaussian_device(int(m), int(n), seed * 100003 + i) for i, (m, n) in enumerate(zip(ms, ns))]
+    Q = [inputs.gaussian_device(int(m), 1, seed * 100003 + 500000 + i) for i, m in enumerate(ms)]
+    WA = [torch.empty_like(a.t()).t() for a in P]
+    WB = [torch.empty_like(b.t()).t() for b in Q]
+
+    def restore():
+        for w, a in zip(WA, P):
+            w.copy_(a)
+        for w, b in zip(WB, Q):
+            w.copy_(b)
+        torch.cuda.synchronize()
+
+    caqr.tune_batched()
+    times = []
+    for it in range(1 + reps):
+        restore()
+        t0 = time.perf_counter()
+        _, info = caqr.ls_solve_batched(WA, WB)
+        t = time.perf_counter() - t0
+        if it >= 1:
+            times.append(t)
+    ok = sum(1 for st in info if st[0] == 0)
+
+    def eta(A, x, b):
+        v = torch.ones(A.shape[1], 1, dtype=torch.float64, device=A.device)
+        for _ in range(30):
+            v = A.t() @ (A @ v)
+            v = v / torch.linalg.norm(v)
+        na = float(torch.linalg.norm(A @ v))
+        r = b - A @ x
+        return float(torch.linalg.norm(A.t() @ r)) / (na * (na * float(torch.linalg.norm(x)) + float(torch.linalg.norm(b))))
+
+    etas = [eta(P[i], WB[i][: P[i].shape[1]], Q[i]) for i in range(0, len(P), len(P) // eta_sample)]
+    restore()
+    t0 = time.perf_counter()
+    for a, b in zip(WA, WB):
+        caqr.ls_solve(a, b)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t = float(np.median(times))
+    flops = float(sum(2.0 * int(m) * int(n) ** 2 - 2.0 * int(n) ** 3 / 3 for m, n in zip(ms, ns)))
+    del P, Q, WA, WB
+    torch.cuda.empty_cache()
+    return {"problems": len(ms), "median_ms": round(t * 1e3, 3), "solves_per_s": round(len(ms) / t, 1),
+            "qr_gflops": round(flops / t / 1e9, 1), "status_ok": ok,
+            "eta_sample_max": max(etas), "plain_ms": round(t_plain * 1e3, 2),
+            "plain_solves_per_s": round(len(ms) / t_plain, 1), "speedup_vs_plain": round(t_plain / t, 2),
+            "timed": "one ls_solve_batched call (host wall clock; it waits for the device) vs one ls_solve per problem"}
+
+
 def served_lines(rates=(200, 500, 1000, 2000), duration=2.0, workers=8, pool=512, budget=64 << 30,
                  eta_sample=8):
     """Served least-squares stream: Poisson arrivals at each rate for `duration`
@@ -355,6 +418,7 @@ def main():
         # plans from the autotuner; one step = one tsqr_factor_batched call
         sec["batched_tsqr_2000_uneven"] = batched_line("f64")
         sec["batched_tsqr_2000_uneven_f32"] = batched_line("f32")
+        sec["batched_ls_2000_uneven"] = batched_ls_line()
         sec["served_ls"] = served_lines()
         out["secondary"] = sec
 

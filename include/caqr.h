@@ -287,6 +287,25 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt);
 /* The plan a batched call with opts == NULL would use for an m-by-n problem. */
 caqr_status_t caqr_batch_plan_for(caqr_handle_t h, int64_t m, int64_t n, caqr_dtype_t dt, caqr_tree_opts_t *plan);
 
+/* Batched least squares: min ||A_i X_i - B_i||_F for `batch` independent
+   problems with n_i <= 64 (FP64).  A_i (m_i x n_i, lda_i) is factored in place
+   by the batched TSQR (one launch per group, the plan of opts or the
+   tuned/default plans); B_i (m_i x nrhs_i, ldb_i) is overwritten by Q_i^T B_i,
+   its first n_i rows by X_i.  Q^T is applied with the stored reflectors one at
+   a time in the order they were made (leaves, then the tree levels
+   bottom-up), so X_i agrees with ls_solve's to rounding, not bitwise.  Waits
+   for the device; info (host array of batch entries) receives each problem's
+   status (CAQR_ERR_SINGULAR with the first zero pivot, CAQR_ERR_NONFINITE);
+   the return value is CAQR_SUCCESS or the first such status.  Errors, before
+   anything is enqueued: CAQR_ERR_INVALID_VALUE (negative sizes, leading
+   dimensions below max(1, m_i), missing arrays or pointers, invalid opts);
+   CAQR_ERR_NOT_SUPPORTED (m_i < n_i, n_i > 64, m_i > 2^31 - 1);
+   CAQR_ERR_ALLOC; CAQR_ERR_DEVICE.  Problems with n_i = 0 or nrhs_i = 0 are
+   left untouched. */
+caqr_status_t ls_solve_batched(caqr_handle_t h, int64_t batch, const int64_t *m, const int64_t *n,
+                               const int64_t *nrhs, double *const *A, const int64_t *lda, double *const *B,
+                               const int64_t *ldb, const caqr_tree_opts_t *opts, caqr_ls_info_t *info);
+
 /* ------------------------------------------------------------------------ */
 /* Served least-squares stream.  Independent requests min ||A_i X_i - B_i||   */
 /* (the solve of ls_solve, Section 3 of the paper for the factorization) are */

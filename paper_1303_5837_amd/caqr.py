@@ -84,7 +84,7 @@ EXPORTS = [
     "caqr_status_string", "caqr_device_count", "tsqr_factor", "caqr_factor", "apply_q", "caqr_factors_destroy",
     "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_set_trace_kinds", "caqr_trace_read",
     "tsqr_factor_batched", "caqr_batch_destroy", "caqr_batch_get_plan", "caqr_batch_get_signs", "caqr_tune_batched",
-    "caqr_batch_plan_for", "caqr_server_create", "caqr_server_submit", "caqr_server_wait", "caqr_server_destroy",
+    "caqr_batch_plan_for", "ls_solve_batched", "caqr_server_create", "caqr_server_submit", "caqr_server_wait", "caqr_server_destroy",
 ]
 
 
@@ -124,6 +124,8 @@ def _lib():
         L.caqr_batch_get_signs.argtypes = [vp, i64, dp]
         L.caqr_tune_batched.argtypes = [vp, i32]
         L.caqr_batch_plan_for.argtypes = [vp, i64, i64, i32, ctypes.POINTER(TreeOpts)]
+        L.ls_solve_batched.argtypes = [vp, i64, pi64, pi64, pi64, ctypes.POINTER(vp), pi64, ctypes.POINTER(vp), pi64,
+                                       ctypes.POINTER(TreeOpts), ctypes.POINTER(LsInfo)]
         L.caqr_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
         L.caqr_server_submit.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(i64)]
         L.caqr_server_wait.argtypes = [vp, i64, ctypes.POINTER(LsInfo), ctypes.POINTER(RequestTimes)]
@@ -385,6 +387,27 @@ def tsqr_batched(As, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0
     _check(_lib().tsqr_factor_batched(h.ptr, k, m, n, ptrs, ld, dt, _opts(leaf_rows, leaves_per_wg),
                                       ctypes.byref(b)), "tsqr_factor_batched")
     return Batch(h, b, As)
+
+
+def ls_solve_batched(As, Bs, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0):
+    """Batched least squares in place (n_i <= 64, float64, column-major CUDA
+    tensors): returns ([X_i = B_i[:n_i]], [(status, index)]); raises only on
+    argument or device errors."""
+    h = handle(device)
+    k = len(As)
+    arr = lambda vals: (ctypes.c_int64 * max(1, k))(*vals)
+    m = arr([int(a.shape[0]) for a in As])
+    n = arr([int(a.shape[1]) for a in As])
+    r = arr([int(b.shape[1]) for b in Bs])
+    la = arr([_ld(a) for a in As])
+    lb = arr([_ld(b) for b in Bs])
+    pa = (ctypes.c_void_p * max(1, k))(*[a.data_ptr() for a in As])
+    pb = (ctypes.c_void_p * max(1, k))(*[b.data_ptr() for b in Bs])
+    info = (LsInfo * max(1, k))()
+    code = _lib().ls_solve_batched(h.ptr, k, m, n, r, pa, la, pb, lb, _opts(leaf_rows, leaves_per_wg), info)
+    if code not in (0, 5, 6):
+        _check(code, "ls_solve_batched")
+    return [b[: a.shape[1]] for a, b in zip(As, Bs)], [(int(info[i].status), int(info[i].index)) for i in range(k)]
 
 
 def tune_batched(device: int = 0, dtype=torch.float64):

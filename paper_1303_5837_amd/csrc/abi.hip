@@ -16,6 +16,7 @@
 #include "../../include/caqr.h"
 #include "abi_internal.hpp"
 #include "kernels.hpp"
+#include "lsb.hpp"
 
 using namespace caqr;
 
@@ -84,6 +85,7 @@ struct caqr_batch_s {
   std::vector<int64_t> m, n;
   std::vector<caqr_tree_opts_t> plan;
   std::vector<int64_t> d_off;           // offset (elements) of D_i in `small`, -1 for n_i = 0
+  std::vector<int64_t> pidx;            // index of problem i in the parameter table, -1 for n_i = 0
   std::vector<caqr::PanelParams> probs; // grouped by (leaf rows, nq); for F32, converted to
   std::vector<caqr::PanelParams32> probs32;  // probs32 before the upload
   std::vector<int2> items;              // (problem within its group, first leaf) per workgroup
@@ -565,6 +567,7 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
   B->n.assign(n, n + batch);
   B->plan.resize(batch);
   B->d_off.assign(batch, -1);
+  B->pidx.assign(batch, -1);
   std::vector<int64_t> L(batch, 0), tau_off(batch, 0);
   int64_t small_elems = 0;
   for (int64_t i = 0; i < batch; ++i) {
@@ -610,6 +613,7 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
           }
         }
         const int local = (int)(B->probs.size() - g.prob0);
+        B->pidx[i] = (int64_t)B->probs.size();
         for (int64_t w = 0; w * p.lpw < L[i]; ++w) B->items.push_back(int2{local, (int)(w * p.lpw)});
         B->probs.push_back(p);
         g.rows += m[i];
@@ -1112,6 +1116,148 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
   std::memcpy(h->tuned_plan[dt], table, sizeof(table));
   h->tuned[dt] = true;
   return CAQR_SUCCESS;
+}
+
+caqr_status_t ls_solve_batched(caqr_handle_t h, int64_t batch, const int64_t *m, const int64_t *n,
+                               const int64_t *nrhs, double *const *A, const int64_t *lda, double *const *B,
+                               const int64_t *ldb, const caqr_tree_opts_t *opts, caqr_ls_info_t *info) {
+  if (batch < 0) return CAQR_ERR_INVALID_VALUE;
+  if (batch > 0 && (!m || !n || !nrhs || !A || !lda || !B || !ldb || !info)) return CAQR_ERR_INVALID_VALUE;
+  if (check_opts(opts)) return CAQR_ERR_INVALID_VALUE;
+  bool unsupported = false;
+  for (int64_t i = 0; i < batch; ++i) {
+    if (m[i] < 0 || n[i] < 0 || nrhs[i] < 0) return CAQR_ERR_INVALID_VALUE;
+    if (lda[i] < std::max<int64_t>(1, m[i]) || ldb[i] < std::max<int64_t>(1, m[i])) return CAQR_ERR_INVALID_VALUE;
+    if ((n[i] > 0 && !A[i]) || (nrhs[i] > 0 && m[i] > 0 && !B[i])) return CAQR_ERR_INVALID_VALUE;
+    if (m[i] < n[i] || n[i] > kNbMax || m[i] > INT32_MAX || nrhs[i] > INT32_MAX) unsupported = true;
+  }
+  if (unsupported) return CAQR_ERR_NOT_SUPPORTED;
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  for (int64_t i = 0; i < batch; ++i) info[i] = caqr_ls_info_t{CAQR_SUCCESS, 0};
+  // the problems with work to do
+  std::vector<int64_t> sel;
+  for (int64_t i = 0; i < batch; ++i)
+    if (n[i] > 0 && nrhs[i] > 0) sel.push_back(i);
+  if (sel.empty()) return CAQR_SUCCESS;
+  DeviceGuard g(h->device);
+  const int64_t K = (int64_t)sel.size();
+  std::vector<int64_t> mm(K), nn(K), ll(K);
+  std::vector<void *> aa(K);
+  for (int64_t s = 0; s < K; ++s) {
+    mm[s] = m[sel[s]];
+    nn[s] = n[sel[s]];
+    ll[s] = lda[sel[s]];
+    aa[s] = A[sel[s]];
+  }
+  caqr_batch_t Bt = nullptr;
+  caqr_status_t st = batch_prepare(h, K, mm.data(), nn.data(), aa.data(), ll.data(), CAQR_F64, opts, &Bt);
+  if (st) return st;
+  if ((st = batch_launch(h, Bt))) {
+    caqr_batch_destroy(Bt);
+    return st;
+  }
+  // Q^T B by the stored reflectors (leaves, then the tree levels bottom-up),
+  // then D and the back substitution
+  std::vector<caqr::LsbProb> probs(K);
+  std::vector<int4> leaf_items, node_items;
+  std::vector<std::pair<int64_t, int64_t>> rounds;  // (first, count) in node_items per level
+  std::vector<int2> solve_items;
+  int64_t nstatus = 0;
+  std::vector<std::vector<int4>> by_level;
+  for (int64_t s = 0; s < K; ++s) {
+    const int64_t i = sel[s];
+    const caqr::PanelParams &pp = Bt->probs[Bt->pidx[s]];
+    caqr::LsbProb &q = probs[s];
+    q.A = pp.A;
+    q.lda = pp.lda;
+    q.m = pp.m;
+    q.b = pp.b;
+    q.L = pp.L;
+    q.h = Bt->plan[s].leaf_rows;
+    q.tau_leaf = pp.tau_leaf;
+    q.tau_node = pp.tau_node;
+    q.d = pp.d;
+    q.B = B[i];
+    q.ldb = ldb[i];
+    q.nrhs = (int)nrhs[i];
+    q.status0 = (int)nstatus;
+    nstatus += nrhs[i];
+    for (int r = 0; r < q.nrhs; ++r) {
+      for (int l = 0; l < q.L; ++l) leaf_items.push_back(int4{(int)s, l, r, 0});
+      int k = 0;
+      for (int half = 1; half < q.L; half <<= 1, ++k) {
+        if ((int)by_level.size() <= k) by_level.resize(k + 1);
+        for (int left = 0; left + half < q.L; left += 2 * half)
+          by_level[k].push_back(int4{(int)s, left, left + half, r});
+      }
+      solve_items.push_back(int2{(int)s, r});
+    }
+  }
+  for (auto &lv : by_level) {
+    rounds.emplace_back((int64_t)node_items.size(), (int64_t)lv.size());
+    node_items.insert(node_items.end(), lv.begin(), lv.end());
+  }
+  if (nstatus > INT32_MAX || (int64_t)leaf_items.size() > INT32_MAX) {
+    caqr_batch_destroy(Bt);
+    return CAQR_ERR_NOT_SUPPORTED;
+  }
+  const size_t o_probs = 0;
+  const size_t o_leaf = (o_probs + K * sizeof(caqr::LsbProb) + 255) & ~(size_t)255;
+  const size_t o_node = (o_leaf + leaf_items.size() * sizeof(int4) + 255) & ~(size_t)255;
+  const size_t o_solve = (o_node + node_items.size() * sizeof(int4) + 255) & ~(size_t)255;
+  const size_t o_stat = (o_solve + solve_items.size() * sizeof(int2) + 255) & ~(size_t)255;
+  const size_t bytes = o_stat + (size_t)nstatus * 2 * sizeof(int64_t);
+  char *buf = nullptr;
+  if (h->ws_limit && bytes > h->ws_limit) st = CAQR_ERR_ALLOC;
+  if (!st && hipMalloc(&buf, bytes) != hipSuccess) st = CAQR_ERR_ALLOC;
+  std::vector<int64_t> stat((size_t)nstatus * 2, 0);
+  auto up = [&](size_t off, const void *src, size_t sz) {
+    return sz == 0 || hipMemcpyAsync(buf + off, src, sz, hipMemcpyHostToDevice, h->stream) == hipSuccess;
+  };
+  if (!st && !(up(o_probs, probs.data(), K * sizeof(caqr::LsbProb)) &&
+               up(o_leaf, leaf_items.data(), leaf_items.size() * sizeof(int4)) &&
+               up(o_node, node_items.data(), node_items.size() * sizeof(int4)) &&
+               up(o_solve, solve_items.data(), solve_items.size() * sizeof(int2))))
+    st = CAQR_ERR_DEVICE;
+  const caqr::LsbProb *dprobs = reinterpret_cast<const caqr::LsbProb *>(buf + o_probs);
+  if (!st && launch_lsb_leaves(dprobs, reinterpret_cast<const int4 *>(buf + o_leaf), (int)leaf_items.size(),
+                               h->stream) != hipSuccess)
+    st = CAQR_ERR_DEVICE;
+  for (const auto &rd : rounds)
+    if (!st && launch_lsb_nodes(dprobs, reinterpret_cast<const int4 *>(buf + o_node) + rd.first, (int)rd.second,
+                                h->stream) != hipSuccess)
+      st = CAQR_ERR_DEVICE;
+  int64_t *dstat = reinterpret_cast<int64_t *>(buf + o_stat);
+  if (!st && launch_lsb_solve(dprobs, reinterpret_cast<const int2 *>(buf + o_solve), (int)solve_items.size(), dstat,
+                              h->stream) != hipSuccess)
+    st = CAQR_ERR_DEVICE;
+  if (!st && hipMemcpyAsync(stat.data(), dstat, stat.size() * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream) !=
+                 hipSuccess)
+    st = CAQR_ERR_DEVICE;
+  if (hipStreamSynchronize(h->stream) != hipSuccess && !st) st = CAQR_ERR_DEVICE;
+  if (buf) (void)hipFree(buf);
+  caqr_batch_destroy(Bt);
+  if (st) return st;
+  caqr_status_t first = CAQR_SUCCESS;
+  for (int64_t s = 0; s < K; ++s) {
+    const caqr::LsbProb &q = probs[s];
+    int64_t zero = 0;
+    bool bad = false;
+    for (int r = 0; r < q.nrhs; ++r) {
+      const int64_t *p2 = &stat[2 * ((size_t)q.status0 + r)];
+      if (p2[0] && !zero) zero = p2[0];
+      bad = bad || p2[1];
+    }
+    caqr_ls_info_t &inf = info[sel[s]];
+    if (zero) {
+      inf.status = CAQR_ERR_SINGULAR;
+      inf.index = zero - 1;
+    } else if (bad) {
+      inf.status = CAQR_ERR_NONFINITE;
+    }
+    if (!first && inf.status) first = (caqr_status_t)inf.status;
+  }
+  return first;
 }
 
 }  // extern "C"

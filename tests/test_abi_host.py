@@ -147,3 +147,30 @@ def test_server_argument_validation_without_device():
     assert sub(None, 100, 10, 1, p, 100, p, 100, p, 10, None) == 1              # NULL ticket
     assert lib.caqr_server_wait(None, 1, None, None) == 1
     assert lib.caqr_server_destroy(None) == 1
+
+
+def test_batched_ls_argument_validation_without_device():
+    """ls_solve_batched checks every problem before the handle."""
+    lib = caqr.library()
+    P = ctypes.c_void_p(0x1000)
+
+    def call(m, n, r, lda=None, ldb=None, pa=True, pb=True, batch=None, info=True, opts=None):
+        k = len(m) if batch is None else batch
+        arr = lambda v: (ctypes.c_int64 * max(1, len(v)))(*v)
+        ptrs = lambda ok: (ctypes.c_void_p * max(1, len(m)))(*([P.value if ok else None] * len(m)))
+        inf = (caqr.LsInfo * max(1, len(m)))()
+        return lib.ls_solve_batched(None, k, arr(m), arr(n), arr(r), ptrs(pa), arr(lda or m), ptrs(pb),
+                                    arr(ldb or m), opts, inf if info else None)
+
+    assert call([100], [10], [1], batch=-1) == 1                 # negative batch
+    assert call([100], [10], [1], info=False) == 1                # no info array
+    assert call([100], [10], [-1]) == 1                           # negative nrhs
+    assert call([100], [10], [1], lda=[99]) == 1                  # lda < m
+    assert call([100], [10], [1], ldb=[99]) == 1                  # ldb < m
+    assert call([100], [10], [1], pa=False) == 1                  # NULL A
+    assert call([100], [10], [1], pb=False) == 1                  # NULL B
+    assert call([100], [65], [1]) == 4                            # n > 64
+    assert call([10], [20], [1]) == 4                             # m < n
+    bad = caqr.TreeOpts(100, 0, 0, 0)
+    assert call([100], [10], [1], opts=ctypes.byref(bad)) == 1    # invalid plan
+    assert call([100, 50], [10, 0], [1, 3]) == 1                  # valid: NULL handle
