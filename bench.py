@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--only", choices=["batched_tsqr", "batched_tsqr_f32", "batched_ls", "served"],
+                    help="run one secondary workload alone and print its line (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -302,6 +304,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        fn = {"batched_tsqr": lambda: batched_line("f64"), "batched_tsqr_f32": lambda: batched_line("f32"),
+              "batched_ls": batched_ls_line, "served": served_lines}[args.only]
+        print(json.dumps({args.only: fn()}))
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     n = args.n
