@@ -364,18 +364,20 @@ caqr_status_t launch_panel_t(caqr_handle_t h, caqr_factors_t F, int idx, hipStre
   return launch_form_t(f, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
 }
 
+// Workgroups from which a panel finishes its tree with one launch per level
+// instead of ticket climbs (and its next panel's update goes level by level
+// too): with hundreds of workgroups, each climb's agent-scope fence (an L2
+// write-back while the other workgroups fill the L2) costs more than a kernel
+// boundary per level.
+constexpr int kLevelLaunchWgs = 128;
+
 // Factor panel idx (the tree climb), then, when asked, form its T factors on
 // the same stream.
-// Workgroups from which a single-panel factorization finishes its tree with
-// one launch per level instead of ticket climbs: with thousands of
-// workgroups, each climb's agent-scope fence (an L2 write-back while the
-// other workgroups fill the L2) costs more than a kernel boundary per level.
-constexpr int kLevelLaunchWgs = 128;
 
 caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form_t, hipStream_t st) {
   const PanelRec &p = F->panels[idx];
   PanelParams pp = panel_params(h, F, p);
-  const bool levels = F->panels.size() == 1 && ceil_div(p.L, F->lpw) >= kLevelLaunchWgs;
+  const bool levels = ceil_div(p.L, F->lpw) >= kLevelLaunchWgs;
   {
     TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
     if (levels) pp.tickets = nullptr;
@@ -390,8 +392,9 @@ caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form
 caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_t c0, int64_t k, hipStream_t st) {
   const PanelRec &p = F->panels[idx];
   UpdateParams u = update_params(h, F, p, F->A + c0 * F->lda, F->lda, k);
-  // the tickets belong to the handle's stream (panel kernels use them too)
-  if (st == h->stream) u.tickets = panel_tickets(h);
+  // the tickets belong to the handle's stream (panel kernels use them too);
+  // tall panels update level by level instead (as their trees are built)
+  if (st == h->stream && p.L < kLevelLaunchWgs) u.tickets = panel_tickets(h);
   // the same test launch_apply_qt makes: one tree-climbing launch, or levels
   const bool one_launch = u.tickets && u.tiles <= kTreeTiles && u.L > 1;
   TraceScope ts(h, one_launch ? CAQR_TRACE_UPDATE_T : CAQR_TRACE_UPDATE_T_LEVELS, idx, p.m, k, p.b, p.L, st);
