@@ -377,8 +377,9 @@ def main():
         "step_ms": [round(x, 4) for x in step_ms],
         "wall_ms_timed_region": round(wall_ms, 2),
         "roofline": {
-            "kernel": "trailing update call Q_s^T C run as leaf_kernel + one node_level_kernel per tree "
-                      "level + scale_rows_kernel (the columns beyond the next panel)",
+            "kernel": "trailing update call Q_s^T C run as leaf_pair_kernel (leaf pairs and the first tree "
+                      "level) + one node_level_kernel per further level + scale_rows_kernel (the columns beyond "
+                      "the next panel)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
             "peak": PEAK_FP64_TFLOPS,

@@ -382,6 +382,24 @@ __global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
   leaf_update<NQ, RT, TRANS>(u, leaf, tile, sm);
 }
 
+// Q^T leaf updates of two neighbouring leaves (2p, 2p + 1) on one tile, then
+// the first tree level's node over them (its rows were just written by this
+// workgroup, so no other workgroup is involved): one workgroup per (pair,
+// tile), and the level launches start at the second level.
+template <int NQ, int RT>
+__global__ void __launch_bounds__(kUThreads, 2) leaf_pair_kernel(UpdateParams u) {
+  __shared__ UpdSmem sm;
+  const int npair = (u.L + 1) / 2;
+  const int pr = blockIdx.x % npair;
+  const int tile = blockIdx.x / npair;
+  leaf_update<NQ, RT, true>(u, 2 * pr, tile, sm);
+  if (2 * pr + 1 < u.L) {
+    leaf_update<NQ, RT, true>(u, 2 * pr + 1, tile, sm);  // ends with a barrier: both leaves' C stored
+    const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
+    node_update<NQ, true>(u, 2 * pr, 2 * pr + 1, tile, sm, vec_ok);
+  }
+}
+
 template <int NQ, bool TRANS>
 __global__ void __launch_bounds__(kUThreads, 2) node_level_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
@@ -453,10 +471,10 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
     hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
     return hipGetLastError();
   }
-  // leaves, then the tree bottom-up (one launch per level, nodes of a level in
-  // parallel), then D
-  hipLaunchKernelGGL((leaf_kernel<NQ, RT, true>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
-  for (int lev = 1; (1 << (lev - 1)) < u.L; ++lev) {
+  // leaf pairs with the first level, then the tree bottom-up (one launch per
+  // level, nodes of a level in parallel), then D
+  hipLaunchKernelGGL((leaf_pair_kernel<NQ, RT>), dim3((u.L + 1) / 2 * u.tiles), dim3(kUThreads), 0, s, u);
+  for (int lev = 2; (1 << (lev - 1)) < u.L; ++lev) {
     UpdateParams v = u;
     v.level = lev;
     const int half = 1 << (lev - 1);
