@@ -357,7 +357,11 @@ caqr_status_t caqr_server_submit(caqr_server_t S, int64_t m, int64_t n, int64_t 
    CAQR_ERR_INVALID_VALUE for an unknown or already released ticket. */
 caqr_status_t caqr_server_wait(caqr_server_t S, int64_t ticket, caqr_ls_info_t *info, caqr_request_times_t *times);
 
-/* Finish every queued request, stop the workers and free the server. */
+/* Finish every queued request, stop the workers and free the server.
+   caqr_server_submit and caqr_server_wait may be called from any host
+   threads concurrently; caqr_server_destroy must not overlap any other call
+   on S, and S is invalid afterwards (tickets not yet waited for are
+   released with it). */
 caqr_status_t caqr_server_destroy(caqr_server_t S);
 
 #ifdef __cplusplus
