@@ -280,6 +280,37 @@ def served_lines(rates=(200, 500, 1000, 2000), duration=2.0, workers=8, pool=512
     return out
 
 
+def inner_block_line(dev, n, reps=3):
+    """The per-level block size variant (leaves and eliminations factored in
+    inner blocks of 16 or 32 columns) against none, on the headline square and
+    the tall TSQR: median times of `reps` runs after one warm-up."""
+    out = {}
+    for key, m2, n2, fn in [("caqr_%dx%d" % (n, n), n, n, lambda A, ib: caqr.caqr(A, nb=64, inner_block=ib)),
+                            ("tsqr_1Mx64", 1 << 20, 64, lambda A, ib: caqr.tsqr(A, inner_block=ib))]:
+        seed = inputs.SEEDS["caqr_8192sq"] if m2 == n else inputs.SEEDS["tsqr_1Mx64"]
+        B0 = caqr.fortran(inputs.gaussian(m2, n2, seed), device=dev)
+        B = torch.empty_like(B0.t()).t()
+        row = {}
+        for ib in (0, 16, 32):
+            times = []
+            for it in range(1 + reps):
+                B.copy_(B0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                G = fn(B, ib)
+                e1.record()
+                torch.cuda.synchronize()
+                if it >= 1:
+                    times.append(e0.elapsed_time(e1))
+                G.close()
+            row["inner_block_%d_ms" % ib] = round(float(np.median(times)), 3)
+        out[key] = row
+        del B0, B
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,8 +323,9 @@ def main():
                     help="run one secondary workload alone and print its line (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design of the sharded variant is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(row blocks sharded over GPUs with one all-gather of R factors per panel is a design, not built)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -422,6 +454,7 @@ def main():
                         "gflops": round((2.0 * m2 * n2 * n2 - 2.0 * n2 ** 3 / 3) / (t * 1e-3) / 1e9, 1),
                         "algorithmic_GBps": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / PEAK_HBM_GBS, 2)}
             del B0, B
+        sec["inner_block"] = inner_block_line(dev, n)
         # uneven batch (2000 problems, m log-uniform in [256, 65536], n in {8,16,32,64}),
         # plans from the autotuner; one step = one tsqr_factor_batched call
         sec["batched_tsqr_2000_uneven"] = batched_line("f64")

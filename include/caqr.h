@@ -75,6 +75,17 @@ typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
  *                  workgroups finishes the device-wide tree with one
  *                  launch per level instead of workgroups signalling each
  *                  other.
+ *   inner_block    block size of the level below the panel (paper, Section
+ *                  3.1, item 1(a): a level factors its part of a b_r-wide
+ *                  panel with the next level's block size b_{r-1}): every
+ *                  leaf and every stacked elimination is factored in inner
+ *                  blocks of 16 or 32 columns, each finished block applied to
+ *                  the columns right of it as one compact-WY transformation.
+ *                  0 or 64: no inner blocking (default).  The reflectors are
+ *                  the same as without it up to rounding, so Y, V, tau, T and
+ *                  every other call are unchanged.  tsqr_factor and
+ *                  caqr_factor only: the batched calls return
+ *                  CAQR_ERR_NOT_SUPPORTED for a nonzero value.
  * The tree is always the binary tree over leaves that pairs leaf i with leaf
  * i + 2^(k-1) at level k (i a multiple of 2^k), the lower index on top;
  * leaves_per_wg only decides which levels run inside a workgroup, so R, Y, V
@@ -82,8 +93,8 @@ typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
 typedef struct {
   int32_t leaf_rows;
   int32_t leaves_per_wg;
-  int32_t reserved0;
-  int32_t reserved1;
+  int32_t inner_block;
+  int32_t reserved; /* 0 */
 } caqr_tree_opts_t;
 
 /* Summary of a factors object (host values). */
@@ -95,6 +106,7 @@ typedef struct {
   int64_t leaves_panel0;  /* leaves of the first panel */
   int32_t depth_panel0;   /* tree levels of the first panel */
   int32_t t_formed;       /* 1 when the T factors are materialized */
+  int32_t inner_block;    /* inner block used (0: none) */
 } caqr_factors_info_t;
 
 /* Least-squares options and report. */

@@ -41,13 +41,14 @@ class CaqrError(RuntimeError):
 
 class TreeOpts(ctypes.Structure):
     _fields_ = [("leaf_rows", ctypes.c_int32), ("leaves_per_wg", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("inner_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FactorsInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nb", ctypes.c_int64), ("panels", ctypes.c_int64),
                 ("leaf_rows", ctypes.c_int32), ("leaves_per_wg", ctypes.c_int32),
-                ("leaves_panel0", ctypes.c_int64), ("depth_panel0", ctypes.c_int32), ("t_formed", ctypes.c_int32)]
+                ("leaves_panel0", ctypes.c_int64), ("depth_panel0", ctypes.c_int32), ("t_formed", ctypes.c_int32),
+                ("inner_block", ctypes.c_int32)]
 
 
 class TraceEntry(ctypes.Structure):
@@ -239,10 +240,10 @@ def _ld(t: torch.Tensor, dtypes=(torch.float64,)) -> int:
     return max(1, t.stride(1) if n > 1 else m)
 
 
-def _opts(leaf_rows=0, leaves_per_wg=0):
-    if not leaf_rows and not leaves_per_wg:
+def _opts(leaf_rows=0, leaves_per_wg=0, inner_block=0):
+    if not leaf_rows and not leaves_per_wg and not inner_block:
         return None
-    return ctypes.byref(TreeOpts(leaf_rows, leaves_per_wg, 0, 0))
+    return ctypes.byref(TreeOpts(leaf_rows, leaves_per_wg, inner_block, 0))
 
 
 class Factors:
@@ -295,23 +296,25 @@ class Factors:
             pass
 
 
-def tsqr(A: torch.Tensor, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0) -> Factors:
+def tsqr(A: torch.Tensor, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0,
+         inner_block: int = 0) -> Factors:
     """In place TSQR of a column-major CUDA tensor; returns the factors (R = F.R)."""
     h = handle(device)
     m, n = A.shape
     f = ctypes.c_void_p()
-    _check(_lib().tsqr_factor(h.ptr, m, n, ctypes.c_void_p(A.data_ptr()), _ld(A), _opts(leaf_rows, leaves_per_wg),
-                              ctypes.byref(f)), "tsqr_factor")
+    _check(_lib().tsqr_factor(h.ptr, m, n, ctypes.c_void_p(A.data_ptr()), _ld(A),
+                              _opts(leaf_rows, leaves_per_wg, inner_block), ctypes.byref(f)), "tsqr_factor")
     return Factors(h, f, A)
 
 
-def caqr(A: torch.Tensor, nb: int = 64, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0) -> Factors:
+def caqr(A: torch.Tensor, nb: int = 64, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0,
+         inner_block: int = 0) -> Factors:
     """In place CAQR (panel width nb) of a column-major CUDA tensor."""
     h = handle(device)
     m, n = A.shape
     f = ctypes.c_void_p()
-    _check(_lib().caqr_factor(h.ptr, m, n, nb, ctypes.c_void_p(A.data_ptr()), _ld(A), _opts(leaf_rows, leaves_per_wg),
-                              ctypes.byref(f)), "caqr_factor")
+    _check(_lib().caqr_factor(h.ptr, m, n, nb, ctypes.c_void_p(A.data_ptr()), _ld(A),
+                              _opts(leaf_rows, leaves_per_wg, inner_block), ctypes.byref(f)), "caqr_factor")
     return Factors(h, f, A)
 
 

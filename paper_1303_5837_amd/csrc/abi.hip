@@ -114,6 +114,7 @@ struct caqr_factors_s {
   int64_t m = 0, n = 0, nb = 0, lda = 0;
   double *A = nullptr;
   int leaf_rows = 256, lpw = 1;
+  int inner_block = 0;      // 16 or 32: leaves and eliminations factored in inner blocks
   std::vector<PanelRec> panels;
   double *small = nullptr;  // tau and d of all panels
   double *tbuf = nullptr;   // T of all panels (eager for caqr_factor, lazy for tsqr_factor)
@@ -381,9 +382,9 @@ caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form
   {
     TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
     if (levels) pp.tickets = nullptr;
-    if (launch_tsqr_panel(pp, F->leaf_rows, st, !levels) != hipSuccess) return CAQR_ERR_DEVICE;
+    if (launch_tsqr_panel(pp, F->leaf_rows, st, !levels, F->inner_block) != hipSuccess) return CAQR_ERR_DEVICE;
     for (int half = F->lpw; levels && half < p.L; half *= 2)
-      if (launch_tsqr_level(pp, half, F->leaf_rows, st) != hipSuccess) return CAQR_ERR_DEVICE;
+      if (launch_tsqr_level(pp, half, F->leaf_rows, st, F->inner_block) != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return form_t ? launch_panel_t(h, F, idx, st) : CAQR_SUCCESS;
 }
@@ -483,7 +484,9 @@ caqr_status_t check_opts(const caqr_tree_opts_t *o) {
   if (o->leaf_rows && !valid_leaf_rows(o->leaf_rows)) return CAQR_ERR_INVALID_VALUE;
   if (o->leaves_per_wg && o->leaves_per_wg != 1 && o->leaves_per_wg != 2 && o->leaves_per_wg != 4)
     return CAQR_ERR_INVALID_VALUE;
-  if (o->reserved0 || o->reserved1) return CAQR_ERR_INVALID_VALUE;
+  if (o->inner_block && o->inner_block != 16 && o->inner_block != 32 && o->inner_block != 64)
+    return CAQR_ERR_INVALID_VALUE;
+  if (o->reserved) return CAQR_ERR_INVALID_VALUE;
   return CAQR_SUCCESS;
 }
 
@@ -496,6 +499,7 @@ caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, dou
   caqr_factors_t f = nullptr;
   caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, ws, &f);
   if (st) return st;
+  f->inner_block = (opts && opts->inner_block < kNbMax) ? opts->inner_block : 0;
   if (n > 0) {
     st = run_factorization(h, f, !tsqr);
     if (st) {
@@ -545,7 +549,7 @@ caqr_status_t check_batch_args(caqr_handle_t h, int64_t batch, const int64_t *m,
   if (batch > 0 && (!m || !n || !A || !lda)) return CAQR_ERR_INVALID_VALUE;
   if (dt != CAQR_F64 && dt != CAQR_F32) return CAQR_ERR_INVALID_VALUE;
   if (check_opts(opts)) return CAQR_ERR_INVALID_VALUE;
-  bool unsupported = false;
+  bool unsupported = opts && opts->inner_block;  // inner blocks: single factorizations only
   for (int64_t i = 0; i < batch; ++i) {
     if (m[i] < 0 || n[i] < 0 || lda[i] < std::max<int64_t>(1, m[i])) return CAQR_ERR_INVALID_VALUE;
     if (n[i] > 0 && !A[i]) return CAQR_ERR_INVALID_VALUE;
@@ -912,6 +916,7 @@ caqr_status_t caqr_factors_get_info(caqr_factors_t F, caqr_factors_info_t *info)
     info->depth_panel0 = depth;
   }
   info->t_formed = F->t_formed ? 1 : 0;
+  info->inner_block = F->inner_block;
   return CAQR_SUCCESS;
 }
 
@@ -1127,7 +1132,7 @@ caqr_status_t ls_solve_batched(caqr_handle_t h, int64_t batch, const int64_t *m,
   if (batch < 0) return CAQR_ERR_INVALID_VALUE;
   if (batch > 0 && (!m || !n || !nrhs || !A || !lda || !B || !ldb || !info)) return CAQR_ERR_INVALID_VALUE;
   if (check_opts(opts)) return CAQR_ERR_INVALID_VALUE;
-  bool unsupported = false;
+  bool unsupported = opts && opts->inner_block;
   for (int64_t i = 0; i < batch; ++i) {
     if (m[i] < 0 || n[i] < 0 || nrhs[i] < 0) return CAQR_ERR_INVALID_VALUE;
     if (lda[i] < std::max<int64_t>(1, m[i]) || ldb[i] < std::max<int64_t>(1, m[i])) return CAQR_ERR_INVALID_VALUE;

@@ -55,10 +55,14 @@ struct UpdateParams {
 // Leaves and tree of one panel.  With device_tree (tickets required), the
 // workgroups climb the whole tree; without, each stops at its own subtree
 // and launch_tsqr_level finishes the tree, one launch per level.
-hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s, bool device_tree = true);
+// inner_block (0, 16 or 32; no effect unless narrower than the panel): every
+// leaf and stacked elimination is factored in inner blocks of that many
+// columns, each block applied to the columns right of it at once.
+hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s, bool device_tree = true,
+                             int inner_block = 0);
 // Level `half` (pairs (left, left + half), left a multiple of 2 half) of one
 // panel's tree; the top level also normalizes the root.
-hipError_t launch_tsqr_level(const PanelParams &p, int half, int leaf_rows, hipStream_t s);
+hipError_t launch_tsqr_level(const PanelParams &p, int half, int leaf_rows, hipStream_t s, int inner_block = 0);
 
 // Independent panels of equal ceil(b/16) = nq and leaf height in one launch:
 // probs (device) holds one PanelParams per problem, items (device) one

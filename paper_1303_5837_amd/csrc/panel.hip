@@ -58,6 +58,27 @@ struct PanelSmem {
   int flag;
 };
 
+// Inner block of a Householder factorization (paper, Section 3.1, item 1(a):
+// a level factors its part of a panel of width b_r with the block size
+// b_{r-1} of the level below).  With an inner block of KB columns a step
+// updates only the columns of its own block; once the block is finished its
+// reflectors are applied to the columns right of it as one transformation,
+// Q_blk^T c = c - V z with z = T^T (V^T c) obtained by forward substitution,
+//     z_k = tau_k (w_k - sum_{l<k} G(l,k) z_l),   w = V^T c,   G = V^T V,
+// so T itself is never formed.  G comes for free: at step j the dot products
+// of the new reflector with the block's finished columns (which hold the
+// earlier reflectors below their diagonals) are G's entries.
+template <class T, int KB, int ROWS>
+struct InnerBlock {
+  T v[KB][ROWS];    // reflector k of the block, by row of the block in registers
+  T g[KB][KB + 1];  // G(l, k), l < k
+};
+template <class T, int ROWS>
+struct InnerBlock<T, 0, ROWS> {
+  T v[1][1];
+  T g[1][1];
+};
+
 // Range of the normal numbers of T.
 template <class T> struct Lim;
 template <> struct Lim<double> {
@@ -69,6 +90,60 @@ template <> struct Lim<float> {
 
 __device__ __forceinline__ int col_group() { return (threadIdx.x >> 6) * 4 + ((threadIdx.x & 63) >> 4); }
 
+// Reflectors k0 .. k0 + 4W*IBS - 1 of a finished inner block (stored in ib)
+// applied to the column slots right of the block (slots SB0 + IBS and on).
+template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK, int IBS, int SB0, class IB>
+__device__ __forceinline__ void inner_block_update(T (&a)[NCH][NS], int b, const PanelSmem<T> &sm, IB &ib) {
+  constexpr int KB = 4 * W * IBS;
+  constexpr int k0 = 4 * W * SB0;
+  const int r = threadIdx.x & 15;
+  __syncthreads();  // the block's last reflector and G entries
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    if (q < SB0 + IBS) continue;
+    T z[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int Dk = (k0 + k) / 16;  // diagonal chunk of reflector k
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int i = 0; i < NACT; ++i) {
+        const bool act = STACK ? (i == Dk || (i >= NB && i <= NB + Dk)) : (i >= Dk);
+        if (!act) continue;
+        const T y = ib.v[k][16 * i + r];
+        if (i & 1) s1 = fma(y, a[i][q], s1);
+        else s0 = fma(y, a[i][q], s0);
+      }
+      z[k] = row16_sum(s0 + s1);
+      // one reflector's rows in flight at a time: hoisting every load of the
+      // unrolled loops would need more registers than the block leaves free
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      T acc = z[k];
+#pragma unroll
+      for (int l = 0; l < k; ++l) acc = fma(-ib.g[l][k], z[l], acc);
+      z[k] = (k0 + k < b) ? sm.taus[k0 + k] * acc : T(0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int Dk = (k0 + k) / 16;
+      if (k0 + k < b) {  // reflectors past the panel width were never stored
+#pragma unroll
+        for (int i = 0; i < NACT; ++i) {
+          const bool act = STACK ? (i == Dk || (i >= NB && i <= NB + Dk)) : (i >= Dk);
+          if (!act) continue;
+          a[i][q] = fma(-ib.v[k][16 * i + r], z[k], a[i][q]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();  // ib is reused by the next block's steps
+}
+
 // One Householder step per column j = 0..b-1 on the block held in a[][]:
 // NACT chunk rows of 16 (LEAF: rows 0..16*NACT-1 of a dense block; STACK: two
 // stacked upper triangles, R_top in chunks 0..NB-1 and R_bot in chunks
@@ -79,15 +154,20 @@ __device__ __forceinline__ int col_group() { return (threadIdx.x >> 6) * 4 + ((t
 // is an unscaled sum of squares, recomputed with power-of-two scaling when
 // alpha^2 + sigma is zero, subnormal or overflows.  T is double, or float for
 // the single-precision batched TSQR (same steps).
-template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK>
-__device__ __forceinline__ void householder_steps(T (&a)[NCH][NS], int b, PanelSmem<T> &sm) {
+// The steps of the 16 columns of diagonal block D.  IBS > 0: inner blocks of
+// IBS column slots (16 IBS columns with four waves), ib holding the current
+// block's reflectors and G.
+template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK, int IBS, class IB>
+__device__ __forceinline__ void diag_block_steps(T (&a)[NCH][NS], int b, PanelSmem<T> &sm, IB *ib, const int D) {
   constexpr int CPS = 4 * W;    // columns per slot
   constexpr int BPS = CPS / 16;  // diagonal blocks per slot
   const int r = threadIdx.x & 15;
   const int c = col_group();
-#pragma unroll
-  for (int D = 0; D < NB; ++D) {
+  {
     const int S = D / BPS;
+    const int SB0 = IBS ? (S / IBS) * IBS : 0;     // first slot of S's inner block
+    const int SB1 = IBS ? SB0 + IBS - 1 : NS - 1;  // last slot the steps update
+    const int k0 = CPS * SB0;                      // first column of the inner block
     for (int jj = 0; jj < 16; ++jj) {
       const int j = 16 * D + jj;
       if (j >= b) break;
@@ -175,7 +255,8 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NS], int b, PanelS
           } else {
             vv = T(0);
           }
-          sm.v[par][16 * i + r] = vv;
+          if constexpr (IBS > 0) ib->v[j - k0][16 * i + r] = vv;
+          else sm.v[par][16 * i + r] = vv;
         }
         if (r == 0) {
           sm.tau[par] = tau;
@@ -186,8 +267,13 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NS], int b, PanelS
       // ---- every thread: w = v^T A(:, col) for its column slots, then the rank-1 update.
       // v is read from LDS where it is used (not held across the reductions).
       // Slots whose columns are all finished (q < S) are skipped.
+      // Blocked: only the inner block's slots; its finished columns give G.
+      const int q0 = IBS ? SB0 : S;
       const T tau = sm.tau[par];
-      const T *vrow = sm.v[par] + r;
+      const T *vrow = r + [&]() -> const T * {
+        if constexpr (IBS > 0) return ib->v[j - k0];
+        else return sm.v[par];
+      }();
       T p[2][NS];  // two partial sums per slot (half the dependency chain)
 #pragma unroll
       for (int q = 0; q < NS; ++q) p[0][q] = p[1][q] = T(0);
@@ -198,17 +284,19 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NS], int b, PanelS
         const T vi = vrow[16 * i];
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-          if (q < S) continue;
+          if (q < q0 || q > SB1) continue;
           p[i & 1][q] = fma(vi, a[i][q], p[i & 1][q]);
         }
       }
       T coef[NS];
 #pragma unroll
       for (int q = 0; q < NS; ++q) {
-        if (q < S) continue;
+        if (q < q0 || q > SB1) continue;
         const T w = row16_sum(p[0][q] + p[1][q]);
         const int col = c + CPS * q;
         coef[q] = (col > j && col < b) ? tau * w : T(0);
+        if constexpr (IBS > 0)
+          if (col < j && r == 0) ib->g[col - k0][j - k0] = w;
       }
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
@@ -217,11 +305,37 @@ __device__ __forceinline__ void householder_steps(T (&a)[NCH][NS], int b, PanelS
         const T vi = vrow[16 * i];
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-          if (q < S) continue;  // finished columns are never updated
+          if (q < S || q > SB1) continue;  // finished columns are never updated
           a[i][q] = fma(-coef[q], vi, a[i][q]);
         }
       }
     }
+  }
+}
+
+// Diagonal blocks D .. NB-1 with inner blocks, each inner block applied to the
+// columns right of it once its last column is done (compile-time recursion,
+// so that every register index stays a constant).
+template <int D, class T, int W, int NCH, int NB, int NS, int NACT, bool STACK, int IBS, class IB>
+__device__ __forceinline__ void blocked_steps(T (&a)[NCH][NS], int b, PanelSmem<T> &sm, IB &ib) {
+  if constexpr (D < NB) {
+    constexpr int CPS = 4 * W;
+    constexpr int BPS = CPS / 16;
+    constexpr int SB0 = (D / BPS / IBS) * IBS;
+    diag_block_steps<T, W, NCH, NB, NS, NACT, STACK, IBS>(a, b, sm, &ib, D);
+    if constexpr ((D + 1) % (BPS * IBS) == 0 && SB0 + IBS < NS)
+      if (CPS * (SB0 + IBS) < b) inner_block_update<T, W, NCH, NB, NS, NACT, STACK, IBS, SB0>(a, b, sm, ib);
+    blocked_steps<D + 1, T, W, NCH, NB, NS, NACT, STACK, IBS>(a, b, sm, ib);
+  }
+}
+
+template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK, int IBS = 0, class IB = InnerBlock<T, 0, 1>>
+__device__ __forceinline__ void householder_steps(T (&a)[NCH][NS], int b, PanelSmem<T> &sm, IB *ib = nullptr) {
+  if constexpr (IBS == 0) {
+#pragma unroll
+    for (int D = 0; D < NB; ++D) diag_block_steps<T, W, NCH, NB, NS, NACT, STACK, 0>(a, b, sm, ib, D);
+  } else {
+    blocked_steps<0, T, W, NCH, NB, NS, NACT, STACK, IBS>(a, b, sm, *ib);
   }
 }
 
@@ -267,14 +381,14 @@ __device__ __forceinline__ void store_upper(const T (&a)[NCH][NS], const PanelPa
 // Eliminate the R at slot `right` against the R at slot `left` (both read from
 // global).  Writes V over the right slot, tau of node `right`, and the new R
 // over the left slot.  The new R stays in chunks 0..NB-1.
-template <class T, int W, int NCH, int NB, int NS>
+template <class T, int W, int NCH, int NB, int NS, int IBS = 0, class IB = InnerBlock<T, 0, 1>>
 __device__ __forceinline__ void combine(T (&a)[NCH][NS], const PanelParamsT<T> &p, int left, int right, int h,
-                                        PanelSmem<T> &sm) {
+                                        PanelSmem<T> &sm, IB *ib = nullptr) {
   const int64_t lrow = (int64_t)left * h, rrow = (int64_t)right * h;
   load_r<T, W, NCH, NB, NS>(a, p, lrow, 0);
   load_r<T, W, NCH, NB, NS>(a, p, rrow, NB);
   __syncthreads();
-  householder_steps<T, W, NCH, NB, NS, 2 * NB, true>(a, p.b, sm);
+  householder_steps<T, W, NCH, NB, NS, 2 * NB, true, IBS>(a, p.b, sm, ib);
   store_upper<T, W, NCH, NB, NS>(a, p, rrow, NB);  // V of the node
   store_upper<T, W, NCH, NB, NS>(a, p, lrow, 0);   // R of the survivor
   __syncthreads();
@@ -335,13 +449,14 @@ struct Slots {
 // this workgroup ends up holding (levels 1-3).  Without DEVICE_TREE the
 // workgroup stops where its subtree needs another workgroup's, and the
 // levels above are eliminated by later launches (one per level).
-template <class T, int W, int RPT, int NB, bool DEVICE_TREE>
+template <class T, int W, int RPT, int NB, bool DEVICE_TREE, int IBS = 0>
 __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
   __shared__ PanelSmem<T> sm;
   constexpr int NS = Slots<W, NB>::value;
   constexpr int CPS = 4 * W;
   constexpr int NCH = (RPT > 2 * NB) ? RPT : 2 * NB;
   constexpr int H = 16 * RPT;
+  __shared__ InnerBlock<T, CPS * IBS, 16 * NCH> ib;
   T a[NCH][NS];
   const int r = threadIdx.x & 15;
   const int c = col_group();
@@ -371,7 +486,7 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
         }
     }
     __syncthreads();
-    householder_steps<T, W, NCH, NB, NS, RPT, false>(a, p.b, sm);
+    householder_steps<T, W, NCH, NB, NS, RPT, false, IBS>(a, p.b, sm, &ib);
     if (full) {
 #pragma unroll
       for (int q = 0; q < NS; ++q) {
@@ -406,13 +521,13 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
           break;
         }
         if (!DEVICE_TREE || !arrive(p, partner, sm)) return;  // another workgroup finishes the node
-        combine<T, W, NCH, NB, NS>(a, p, rt, partner, H, sm);
+        combine<T, W, NCH, NB, NS, IBS>(a, p, rt, partner, H, sm, &ib);
       } else {  // right child: node id rt, left sibling rt - half
         const int left = rt - half;
         if (left < leaf0) {
           if (!DEVICE_TREE || !arrive(p, rt, sm)) return;
         }
-        combine<T, W, NCH, NB, NS>(a, p, left, rt, H, sm);
+        combine<T, W, NCH, NB, NS, IBS>(a, p, left, rt, H, sm, &ib);
         rt = left;
       }
     }
@@ -421,21 +536,22 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
   }
 }
 
-template <int RPT, int NB, bool DEVICE_TREE>
+template <int RPT, int NB, bool DEVICE_TREE, int IBS>
 __global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_panel_kernel(PanelParams p) {
-  panel_body<double, kPanelWaves, RPT, NB, DEVICE_TREE>(p, blockIdx.x * p.lpw);
+  panel_body<double, kPanelWaves, RPT, NB, DEVICE_TREE, IBS>(p, blockIdx.x * p.lpw);
 }
 
 // One device level of a single panel's tree (when the leaves' launch stops
 // at the workgroups' subtrees): workgroup i eliminates slot left + half
 // against slot left = 2 half i, and normalizes the root at the top level.
-template <int NB>
+template <int NB, int IBS>
 __global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_level_kernel(PanelParams p, int half, int h) {
   constexpr int NS = Slots<kPanelWaves, NB>::value;
   __shared__ PanelSmem<double> sm;
+  __shared__ InnerBlock<double, 4 * kPanelWaves * IBS, 32 * NB> ib;
   double a[2 * NB][NS];
   const int left = 2 * half * (int)blockIdx.x;
-  combine<double, kPanelWaves, 2 * NB, NB, NS>(a, p, left, left + half, h, sm);
+  combine<double, kPanelWaves, 2 * NB, NB, NS, IBS>(a, p, left, left + half, h, sm, &ib);
   if (2 * half >= p.L) finish_root<double, kPanelWaves, 2 * NB, NB, NS>(a, p, sm);
 }
 
@@ -473,32 +589,48 @@ __global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_tree_level_kernel(co
 
 constexpr int kPanelThreads = 64 * kPanelWaves;
 
-template <int RPT, int NB>
+template <int RPT, int NB, int IBS>
 hipError_t launch_panel_t(const PanelParams &p, bool device_tree, hipStream_t s) {
   const int grid = (p.L + p.lpw - 1) / p.lpw;
   if (device_tree)
-    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NB, true>), dim3(grid), dim3(kPanelThreads), 0, s, p);
+    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NB, true, IBS>), dim3(grid), dim3(kPanelThreads), 0, s, p);
   else
-    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NB, false>), dim3(grid), dim3(kPanelThreads), 0, s, p);
+    hipLaunchKernelGGL((tsqr_panel_kernel<RPT, NB, false, IBS>), dim3(grid), dim3(kPanelThreads), 0, s, p);
   return hipGetLastError();
 }
 
+// Inner block slots in effect for a panel of NB diagonal blocks: none unless
+// the inner block is narrower than the panel.
+template <int RPT, int NB>
+hipError_t launch_panel_ib(const PanelParams &p, bool device_tree, int ibs, hipStream_t s) {
+  if (ibs == 1 && NB > 1) return launch_panel_t<RPT, NB, (NB > 1 ? 1 : 0)>(p, device_tree, s);
+  if (ibs == 2 && NB > 2) return launch_panel_t<RPT, NB, (NB > 2 ? 2 : 0)>(p, device_tree, s);
+  return launch_panel_t<RPT, NB, 0>(p, device_tree, s);
+}
+
 template <int RPT>
-hipError_t launch_panel_nq(const PanelParams &p, bool device_tree, hipStream_t s) {
+hipError_t launch_panel_nq(const PanelParams &p, bool device_tree, int ibs, hipStream_t s) {
   switch ((p.b + 15) / 16) {
-    case 1: return launch_panel_t<RPT, 1>(p, device_tree, s);
-    case 2: return launch_panel_t<RPT, 2>(p, device_tree, s);
-    case 3: return launch_panel_t<RPT, 3>(p, device_tree, s);
-    case 4: return launch_panel_t<RPT, 4>(p, device_tree, s);
+    case 1: return launch_panel_ib<RPT, 1>(p, device_tree, ibs, s);
+    case 2: return launch_panel_ib<RPT, 2>(p, device_tree, ibs, s);
+    case 3: return launch_panel_ib<RPT, 3>(p, device_tree, ibs, s);
+    case 4: return launch_panel_ib<RPT, 4>(p, device_tree, ibs, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int NB>
+template <int NB, int IBS>
 hipError_t launch_level_single_t(const PanelParams &p, int half, int h, hipStream_t s) {
   const int nodes = (p.L - half + 2 * half - 1) / (2 * half);
-  hipLaunchKernelGGL((tsqr_level_kernel<NB>), dim3(nodes), dim3(kPanelThreads), 0, s, p, half, h);
+  hipLaunchKernelGGL((tsqr_level_kernel<NB, IBS>), dim3(nodes), dim3(kPanelThreads), 0, s, p, half, h);
   return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_level_ib(const PanelParams &p, int half, int h, int ibs, hipStream_t s) {
+  if (ibs == 1 && NB > 1) return launch_level_single_t<NB, (NB > 1 ? 1 : 0)>(p, half, h, s);
+  if (ibs == 2 && NB > 2) return launch_level_single_t<NB, (NB > 2 ? 2 : 0)>(p, half, h, s);
+  return launch_level_single_t<NB, 0>(p, half, h, s);
 }
 
 template <class T, int RPT, int NB>
@@ -568,24 +700,28 @@ hipError_t launch_tsqr_tree_level(const PanelParams32 *probs, const int4 *nodes,
   return launch_level<float>(probs, nodes, nnodes, nq, s);
 }
 
-hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s, bool device_tree) {
+hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s, bool device_tree, int inner_block) {
   if (p.b < 1 || p.b > kMaxB || p.L < 1 || p.lpw < 1) return hipErrorInvalidValue;
   if (device_tree && !p.tickets) return hipErrorInvalidValue;
+  if (inner_block % 16 || inner_block < 0) return hipErrorInvalidValue;
+  const int ibs = inner_block / 16;  // 16-column slots per inner block (four waves)
   switch (leaf_rows) {
-    case 64: return launch_panel_nq<4>(p, device_tree, s);
-    case 128: return launch_panel_nq<8>(p, device_tree, s);
-    case 256: return launch_panel_nq<16>(p, device_tree, s);
+    case 64: return launch_panel_nq<4>(p, device_tree, ibs, s);
+    case 128: return launch_panel_nq<8>(p, device_tree, ibs, s);
+    case 256: return launch_panel_nq<16>(p, device_tree, ibs, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_tsqr_level(const PanelParams &p, int half, int leaf_rows, hipStream_t s) {
+hipError_t launch_tsqr_level(const PanelParams &p, int half, int leaf_rows, hipStream_t s, int inner_block) {
   if (p.b < 1 || p.b > kMaxB || half < 1 || half >= p.L) return hipErrorInvalidValue;
+  if (inner_block % 16 || inner_block < 0) return hipErrorInvalidValue;
+  const int ibs = inner_block / 16;
   switch ((p.b + 15) / 16) {
-    case 1: return launch_level_single_t<1>(p, half, leaf_rows, s);
-    case 2: return launch_level_single_t<2>(p, half, leaf_rows, s);
-    case 3: return launch_level_single_t<3>(p, half, leaf_rows, s);
-    case 4: return launch_level_single_t<4>(p, half, leaf_rows, s);
+    case 1: return launch_level_ib<1>(p, half, leaf_rows, ibs, s);
+    case 2: return launch_level_ib<2>(p, half, leaf_rows, ibs, s);
+    case 3: return launch_level_ib<3>(p, half, leaf_rows, ibs, s);
+    case 4: return launch_level_ib<4>(p, half, leaf_rows, ibs, s);
     default: return hipErrorInvalidValue;
   }
 }

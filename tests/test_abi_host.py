@@ -174,3 +174,31 @@ def test_batched_ls_argument_validation_without_device():
     bad = caqr.TreeOpts(100, 0, 0, 0)
     assert call([100], [10], [1], opts=ctypes.byref(bad)) == 1    # invalid plan
     assert call([100, 50], [10, 0], [1, 3]) == 1                  # valid: NULL handle
+
+
+def test_inner_block_validation_without_device():
+    """inner_block: 0, 16, 32 or 64 for the single factorizations; the batched
+    calls accept only 0 (NOT_SUPPORTED otherwise, after every argument check)."""
+    lib = caqr.library()
+    A = ctypes.c_void_p(0x1000)
+    for ib in (0, 16, 32, 64):  # valid: the NULL handle is what fails
+        assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, ib, 0))) == 1
+        f = ctypes.c_void_p()
+        o = caqr.TreeOpts(0, 0, ib, 0)
+        assert lib.caqr_factor(None, 100, 100, 64, A, 100, ctypes.byref(o), ctypes.byref(f)) == 1
+    for ib in (8, 24, 48, -16, 128, 1):
+        assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, ib, 0))) == 1
+    assert _tsqr(10, 20, A, 10, ctypes.byref(caqr.TreeOpts(0, 0, 16, 0))) == 4  # m < n still NOT_SUPPORTED
+    assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, 16, 7))) == 1  # reserved must be 0
+    M = (ctypes.c_int64 * 1)(100)
+    N = (ctypes.c_int64 * 1)(8)
+    P = (ctypes.c_void_p * 1)(A.value)
+    f = ctypes.c_void_p()
+    o = caqr.TreeOpts(0, 0, 16, 0)
+    assert lib.tsqr_factor_batched(None, 1, M, N, P, M, caqr.F64, ctypes.byref(o), ctypes.byref(f)) == 4
+    o = caqr.TreeOpts(0, 0, 24, 0)
+    assert lib.tsqr_factor_batched(None, 1, M, N, P, M, caqr.F64, ctypes.byref(o), ctypes.byref(f)) == 1
+    R = (ctypes.c_int64 * 1)(1)
+    inf = (caqr.LsInfo * 1)()
+    o = caqr.TreeOpts(0, 0, 32, 0)
+    assert lib.ls_solve_batched(None, 1, M, N, R, P, M, P, M, ctypes.byref(o), inf) == 4
