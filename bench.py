@@ -284,6 +284,11 @@ def inner_block_line(dev, n, reps=3):
     """The per-level block size variant (leaves and eliminations factored in
     inner blocks of 16 or 32 columns) against none, on the headline square and
     the tall TSQR: median times of `reps` runs after one warm-up."""
+    import numpy as np
+    import torch
+
+    from paper_1303_5837_amd import caqr, inputs
+
     out = {}
     for key, m2, n2, fn in [("caqr_%dx%d" % (n, n), n, n, lambda A, ib: caqr.caqr(A, nb=64, inner_block=ib)),
                             ("tsqr_1Mx64", 1 << 20, 64, lambda A, ib: caqr.tsqr(A, inner_block=ib))]:
