@@ -63,6 +63,27 @@ def update_traffic_per_call():
     return int(m_b.group(1)) if h.hexdigest() == m_h.group(1) else None
 
 
+def executed_flops(m: int, n: int, nb: int, h: int = 256) -> float:
+    """Flops the CAQR factorization executes (the LAPACK count 4n^3/3 of a square
+    matrix omits the tree's redundant work): per panel s (rows m_s, width b,
+    L = ceil(m_s / h) leaves) the leaf QRs (2 h_i b^2 - 2b^3/3 each, h_i the
+    leaf's rows, at least b), L - 1 stacked eliminations (2b^3/3 each) and the
+    update of the n_t columns right of it (update_flops); T formation is not
+    counted."""
+    total = 0.0
+    for c0 in range(0, n, nb):
+        ms, b = m - c0, min(nb, n - c0)
+        L = -(-ms // h)
+        for i in range(L):
+            hi = max(min(h, ms - i * h), b)
+            total += 2.0 * hi * b * b - 2.0 * b ** 3 / 3.0
+        total += (L - 1) * 2.0 * b ** 3 / 3.0
+        nt = n - c0 - b
+        if nt > 0:
+            total += update_flops(ms, nt, b, L)
+    return total
+
+
 def panel_bytes(rows: int, b: int) -> float:
     """Algorithmic HBM bytes of one panel factorization: read A, write Y/R."""
     return 16.0 * rows * b
@@ -411,7 +432,10 @@ def main():
                    "tree": "binary per panel: workgroup leaf, workgroup, device", "seed": inputs.SEEDS["caqr_8192sq"],
                    "flop_count": "LAPACK 4n^3/3"},
         "pct_fp64_peak": round(100.0 * gflops / (PEAK_FP64_TFLOPS * 1e3), 2),
+        "gflops_executed": round(executed_flops(n, n, nb) / (ms * 1e-3) / 1e9, 2),
+        "executed_flop_count": "leaf QRs + stacked eliminations + trailing updates with their tree nodes",
         "step_ms": [round(x, 4) for x in step_ms],
+        "step_ms_p10_p50_p90": [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],
         "wall_ms_timed_region": round(wall_ms, 2),
         "roofline": {
             "kernel": "trailing update call Q_s^T C run as leaf_pair_kernel (leaf pairs and the first tree "
@@ -484,6 +508,14 @@ def main():
             "sample": f"oracle Householder QR of a {ns}x{ns} N(0,1) matrix (seed 2), one run of {dt:.1f} s, "
                       f"LAPACK flop count 4n^3/3, OpenMP over trailing columns",
         }
+        # labelled secondary CPU reference (not the baseline): the host LAPACK
+        # QR (numpy.linalg.qr, R only) of the same matrix on all host cores
+        t0 = time.perf_counter()
+        np.linalg.qr(S, mode="r")
+        dt = time.perf_counter() - t0
+        out["cpu_reference_lapack"] = {"value": round(4.0 * ns ** 3 / 3.0 / dt / 1e9, 3), "unit": "GFLOP/s",
+                                       "seconds": round(dt, 2), "kind": "host LAPACK dgeqrf via numpy.linalg.qr",
+                                       "host_cpus": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 
