@@ -68,13 +68,21 @@ struct PanelSmem {
 // so T itself is never formed.  G comes for free: at step j the dot products
 // of the new reflector with the block's finished columns (which hold the
 // earlier reflectors below their diagonals) are G's entries.
+// With kShared, w and z of every column right of the block pass through LDS
+// so that each reflector is read once for all of them; that takes 16 KB more
+// and is used where two workgroups still fit in a CU's 160 KB (with margin
+// for the allocation granule).
 template <class T, int KB, int ROWS>
 struct InnerBlock {
+  static constexpr bool kShared =
+      sizeof(T) * (KB * ROWS + KB * (KB + 1) + 4 * 16 * KB) + sizeof(PanelSmem<T>) <= 78 * 1024;
   T v[KB][ROWS];    // reflector k of the block, by row of the block in registers
   T g[KB][KB + 1];  // G(l, k), l < k
+  T z[kShared ? 4 : 1][16][kShared ? KB : 1];  // w, then z, per (column slot, column group)
 };
 template <class T, int ROWS>
 struct InnerBlock<T, 0, ROWS> {
+  static constexpr bool kShared = false;
   T v[1][1];
   T g[1][1];
 };
@@ -92,19 +100,102 @@ __device__ __forceinline__ int col_group() { return (threadIdx.x >> 6) * 4 + ((t
 
 // Reflectors k0 .. k0 + 4W*IBS - 1 of a finished inner block (stored in ib)
 // applied to the column slots right of the block (slots SB0 + IBS and on).
+// Reflector by reflector, so that each one's rows are read from LDS once for
+// every slot: w = V^T c, then z = T^T w per slot (forward substitution), then
+// c -= V z.  w and z pass through ib.z: a column's 16 lanes hold the same
+// value, one lane stores it and the same wave reads it back (no barrier).
 template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK, int IBS, int SB0, class IB>
-__device__ __forceinline__ void inner_block_update(T (&a)[NCH][NS], int b, const PanelSmem<T> &sm, IB &ib) {
+__device__ __forceinline__ void inner_block_update_shared(T (&a)[NCH][NS], int b, const PanelSmem<T> &sm, IB &ib) {
+  static_assert(W == 4 && NS <= 4, "ib.z is laid out for four waves");
+  constexpr int KB = 4 * W * IBS;
+  constexpr int k0 = 4 * W * SB0;
+  constexpr int Q0 = SB0 + IBS;  // first slot right of the block
+  const int r = threadIdx.x & 15;
+  const int c = col_group();
+  __syncthreads();  // the block's last reflector and G entries
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    if (k0 + k >= b) continue;  // reflectors past the panel width were never stored
+    const int Dk = (k0 + k) / 16;  // diagonal chunk of reflector k
+    T y[NACT];
+#pragma unroll
+    for (int i = 0; i < NACT; ++i) {
+      const bool act = STACK ? (i == Dk || (i >= NB && i <= NB + Dk)) : (i >= Dk);
+      y[i] = act ? ib.v[k][16 * i + r] : T(0);
+    }
+#pragma unroll
+    for (int q = Q0; q < NS; ++q) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int i = 0; i < NACT; ++i) {
+        const bool act = STACK ? (i == Dk || (i >= NB && i <= NB + Dk)) : (i >= Dk);
+        if (!act) continue;
+        if (i & 1) s1 = fma(y[i], a[i][q], s1);
+        else s0 = fma(y[i], a[i][q], s0);
+      }
+      const T w = row16_sum(s0 + s1);
+      if (r == 0) ib.z[q][c][k] = w;
+    }
+    // one reflector's rows in flight at a time: hoisting every load of the
+    // unrolled loops would need more registers than the block leaves free
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int q = Q0; q < NS; ++q) {
+    T z[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) z[k] = ib.z[q][c][k];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      T acc = z[k];
+#pragma unroll
+      for (int l = 0; l < k; ++l) acc = fma(-ib.g[l][k], z[l], acc);
+      z[k] = (k0 + k < b) ? sm.taus[k0 + k] * acc : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+      if (r == 0) ib.z[q][c][k] = z[k];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    if (k0 + k >= b) continue;
+    const int Dk = (k0 + k) / 16;
+    T y[NACT];
+#pragma unroll
+    for (int i = 0; i < NACT; ++i) {
+      const bool act = STACK ? (i == Dk || (i >= NB && i <= NB + Dk)) : (i >= Dk);
+      y[i] = act ? ib.v[k][16 * i + r] : T(0);
+    }
+#pragma unroll
+    for (int q = Q0; q < NS; ++q) {
+      const T zk = ib.z[q][c][k];
+#pragma unroll
+      for (int i = 0; i < NACT; ++i) {
+        const bool act = STACK ? (i == Dk || (i >= NB && i <= NB + Dk)) : (i >= Dk);
+        if (!act) continue;
+        a[i][q] = fma(-y[i], zk, a[i][q]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();  // ib is reused by the next block's steps
+}
+
+// The same, one column slot at a time with w and z in registers (each
+// reflector's rows read again for every slot; no LDS beyond v and G).
+template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK, int IBS, int SB0, class IB>
+__device__ __forceinline__ void inner_block_update_slotwise(T (&a)[NCH][NS], int b, const PanelSmem<T> &sm, IB &ib) {
   constexpr int KB = 4 * W * IBS;
   constexpr int k0 = 4 * W * SB0;
   const int r = threadIdx.x & 15;
   __syncthreads();  // the block's last reflector and G entries
 #pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    if (q < SB0 + IBS) continue;
+  for (int q = SB0 + IBS; q < NS; ++q) {
     T z[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-      const int Dk = (k0 + k) / 16;  // diagonal chunk of reflector k
+      const int Dk = (k0 + k) / 16;
       T s0 = T(0), s1 = T(0);
 #pragma unroll
       for (int i = 0; i < NACT; ++i) {
@@ -115,8 +206,6 @@ __device__ __forceinline__ void inner_block_update(T (&a)[NCH][NS], int b, const
         else s0 = fma(y, a[i][q], s0);
       }
       z[k] = row16_sum(s0 + s1);
-      // one reflector's rows in flight at a time: hoisting every load of the
-      // unrolled loops would need more registers than the block leaves free
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
@@ -142,6 +231,14 @@ __device__ __forceinline__ void inner_block_update(T (&a)[NCH][NS], int b, const
     }
   }
   __syncthreads();  // ib is reused by the next block's steps
+}
+
+template <class T, int W, int NCH, int NB, int NS, int NACT, bool STACK, int IBS, int SB0, class IB>
+__device__ __forceinline__ void inner_block_update(T (&a)[NCH][NS], int b, const PanelSmem<T> &sm, IB &ib) {
+  if constexpr (IB::kShared)
+    inner_block_update_shared<T, W, NCH, NB, NS, NACT, STACK, IBS, SB0>(a, b, sm, ib);
+  else
+    inner_block_update_slotwise<T, W, NCH, NB, NS, NACT, STACK, IBS, SB0>(a, b, sm, ib);
 }
 
 // One Householder step per column j = 0..b-1 on the block held in a[][]:
