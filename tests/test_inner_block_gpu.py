@@ -32,6 +32,8 @@ TSQR_CASES = [
     (40000, 17, 256, 1, 16),  # 157 workgroups: tree levels launched one by one
     (40000, 40, 128, 4, 32),  # ticket climbs over 79 workgroups
     (5000, 16, 256, 0, 16),   # block as wide as the panel: no inner blocking
+    (33000, 64, 128, 2, 32),  # 128-row leaves: w and z of the block update through LDS
+    (33000, 64, 256, 1, 16),
 ]
 
 
@@ -60,6 +62,7 @@ CAQR_CASES = [
     (777, 200, 32, 16),
     (700, 90, 17, 16),     # panels of 17 columns: a one-column second block
     (3000, 1000, 64, 32),
+    (1200, 600, 64, 32),   # with 128-row leaves (see the test)
 ]
 
 
@@ -68,7 +71,7 @@ def test_caqr_matches_oracle(m, n, nb, ib):
     require_gpu()
     banner(f"inner-block caqr parity m={m} n={n} nb={nb} inner_block={ib}")
     A = inputs.gaussian(m, n, 4000 + m + n + ib)
-    F, R = caqr_gpu(A, nb=nb, inner_block=ib)
+    F, R = caqr_gpu(A, nb=nb, inner_block=ib, leaf_rows=128 if (m, n) == (1200, 600) else 0)
     oracle.set_threads(16)
     Rref = oracle.qr_r(A)
     assert np.all(np.diag(R) >= 0)
