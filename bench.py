@@ -337,6 +337,42 @@ def inner_block_line(dev, n, reps=3):
     return out
 
 
+def measured_peaks(dev):
+    """Achievable rates on this device, as context for the spec peaks: HBM from a
+    plain 512 MiB device-to-device copy (bytes read + written / time) and FP64
+    matrix throughput from the vendor BLAS (torch.matmul on float64, 8192^3)."""
+    import numpy as np
+    import torch
+
+    def timed(fn, reps):
+        ts = []
+        for it in range(reps + 2):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if it >= 2:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    src = torch.empty(64 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src), 10)
+    hbm = 2.0 * src.numel() * 8 / (t * 1e-3) / 1e9
+    del src, dst
+    a = torch.randn(8192, 8192, dtype=torch.float64, device=dev)
+    b = torch.randn(8192, 8192, dtype=torch.float64, device=dev)
+    t = timed(lambda: torch.matmul(a, b), 5)
+    dg = 2.0 * 8192 ** 3 / (t * 1e-3) / 1e12
+    del a, b
+    torch.cuda.empty_cache()
+    return {"hbm_copy_GBps": round(hbm, 1), "hbm_spec_GBps": PEAK_HBM_GBS,
+            "dgemm_8192_TFLOPs": round(dg, 2), "fp64_spec_TFLOPs": PEAK_FP64_TFLOPS,
+            "how": "512 MiB device copy (read + write bytes); torch.matmul float64 8192^3 (vendor BLAS)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -459,6 +495,7 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_secondary:
+        out["peaks_measured"] = measured_peaks(dev)
         sec = {}
         for (m2, n2, key) in [(1 << 20, 64, "tsqr_1Mx64"), (4096, 32, "tsqr_4096x32")]:
             B0 = caqr.fortran(inputs.gaussian(m2, n2, inputs.SEEDS[key]), device=dev)
