@@ -20,7 +20,9 @@
 // The tree is the binary tree over leaves that pairs i with i + 2^(k-1) at
 // level k (i a multiple of 2^k), the lower index on top.  Node ids are the
 // index of the right (eliminated) child.  The stacked elimination is computed
-// once, by one workgroup (the paper computes it at both partners).
+// once, by one workgroup (the paper computes it at both partners).  With an
+// inner block (the block size of the level below, Section 3.1 item 1(a)),
+// leaves and eliminations are factored block by block (InnerBlock below).
 //
 // Outputs: R (b-by-b, non-negative diagonal) in the top rows of the panel; leaf
 // reflectors below each leaf's diagonal; each node's V (upper triangular) over
