@@ -337,6 +337,23 @@ def inner_block_line(dev, n, reps=3):
     return out
 
 
+def served_line_child(workers, hw_queues=16):
+    """The served stream in a child process started with GPU_MAX_HW_QUEUES =
+    2 x workers (the HIP runtime reads it once, at initialization): each worker
+    drives two streams, and with the default four hardware queues the workers'
+    streams would share queues and run one after the other."""
+    import subprocess
+
+    env = dict(os.environ, GPU_MAX_HW_QUEUES=str(max(hw_queues, 2 * workers)))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--only", "served", "--served-workers",
+                        str(workers)], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": f"served child exited {r.returncode}", "stderr_tail": r.stderr[-2000:]}
+    line = json.loads(r.stdout.strip().splitlines()[-1])["served"]
+    line["hw_queues"] = int(env["GPU_MAX_HW_QUEUES"])
+    return line
+
+
 def measured_peaks(dev):
     """Achievable rates on this device, as context for the spec peaks: HBM from a
     plain 512 MiB device-to-device copy (bytes read + written / time) and FP64
@@ -383,6 +400,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--only", choices=["batched_tsqr", "batched_tsqr_f32", "batched_ls", "served"],
                     help="run one secondary workload alone and print its line (for profiling)")
+    ap.add_argument("--served-workers", type=int, default=8, help="worker threads of the served stream's server")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -400,7 +418,7 @@ def main():
         sys.exit(2)
     if args.only:
         fn = {"batched_tsqr": lambda: batched_line("f64"), "batched_tsqr_f32": lambda: batched_line("f32"),
-              "batched_ls": batched_ls_line, "served": served_lines}[args.only]
+              "batched_ls": batched_ls_line, "served": lambda: served_lines(workers=args.served_workers)}[args.only]
         print(json.dumps({args.only: fn()}))
         return
     dev = torch.device("cuda:0")
@@ -526,7 +544,7 @@ def main():
         sec["batched_tsqr_2000_uneven"] = batched_line("f64")
         sec["batched_tsqr_2000_uneven_f32"] = batched_line("f32")
         sec["batched_ls_2000_uneven"] = batched_ls_line()
-        sec["served_ls"] = served_lines()
+        sec["served_ls"] = served_line_child(args.served_workers)
         out["secondary"] = sec
 
     if not args.no_cpu_baseline:

@@ -328,6 +328,12 @@ caqr_status_t ls_solve_batched(caqr_handle_t h, int64_t batch, const int64_t *m,
 /* workspace, all carved from one device allocation made at creation, so no */
 /* device memory is allocated or freed while serving.  A request's result is */
 /* bitwise that of ls_solve on the same problem, whatever else is served.    */
+/* Each worker drives two streams (its factorization's chain and the wide    */
+/* trailing updates); the HIP runtime maps a process's streams onto         */
+/* GPU_MAX_HW_QUEUES hardware queues (4 by default), and streams sharing a  */
+/* queue run one after the other.  Start the serving process with at least  */
+/* 2 x workers queues (e.g. GPU_MAX_HW_QUEUES=16 for 8 workers) for the      */
+/* workers to overlap.                                                      */
 /* ------------------------------------------------------------------------ */
 
 typedef struct caqr_server_s *caqr_server_t;
