@@ -337,6 +337,43 @@ def inner_block_line(dev, n, reps=3):
     return out
 
 
+TSQR_LINES = {"tsqr_1Mx64": (1 << 20, 64), "tsqr_4096x32": (4096, 32)}
+
+
+def tsqr_line(key):
+    """One tall-skinny TSQR (default tree) timed by HIP events: median, p10 and
+    p90 of 20 calls (50 for 4096 x 32) after 5 warm-ups; algorithmic bytes 16mn
+    (read A, write Y/R)."""
+    import numpy as np
+    import torch
+
+    from paper_1303_5837_amd import caqr, inputs
+
+    m2, n2 = TSQR_LINES[key]
+    B0 = caqr.fortran(inputs.gaussian(m2, n2, inputs.SEEDS[key]))
+    B = torch.empty_like(B0.t()).t()
+    times = []
+    reps = 20 if m2 > 4096 else 50
+    for it in range(5 + reps):
+        B.copy_(B0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        G = caqr.tsqr(B)
+        e1.record()
+        torch.cuda.synchronize()
+        if it >= 5:
+            times.append(e0.elapsed_time(e1))
+        G.close()
+    t = float(np.median(times))
+    gbs = panel_bytes(m2, n2) / (t * 1e-3) / 1e9
+    del B0, B
+    return {"median_us": round(t * 1e3, 2), "p10_us": round(float(np.percentile(times, 10)) * 1e3, 2),
+            "p90_us": round(float(np.percentile(times, 90)) * 1e3, 2),
+            "gflops": round((2.0 * m2 * n2 * n2 - 2.0 * n2 ** 3 / 3) / (t * 1e-3) / 1e9, 1),
+            "algorithmic_GBps": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / PEAK_HBM_GBS, 2)}
+
+
 def served_line_child(workers, hw_queues=16):
     """The served stream in a child process started with GPU_MAX_HW_QUEUES =
     2 x workers (the HIP runtime reads it once, at initialization): each worker
@@ -398,7 +435,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--only", choices=["batched_tsqr", "batched_tsqr_f32", "batched_ls", "served"],
+    ap.add_argument("--only", choices=["batched_tsqr", "batched_tsqr_f32", "batched_ls", "served", "tsqr_1Mx64",
+                                       "tsqr_4096x32"],
                     help="run one secondary workload alone and print its line (for profiling)")
     ap.add_argument("--served-workers", type=int, default=8, help="worker threads of the served stream's server")
     args = ap.parse_args()
@@ -418,7 +456,8 @@ def main():
         sys.exit(2)
     if args.only:
         fn = {"batched_tsqr": lambda: batched_line("f64"), "batched_tsqr_f32": lambda: batched_line("f32"),
-              "batched_ls": batched_ls_line, "served": lambda: served_lines(workers=args.served_workers)}[args.only]
+              "batched_ls": batched_ls_line, "served": lambda: served_lines(workers=args.served_workers),
+              "tsqr_1Mx64": lambda: tsqr_line("tsqr_1Mx64"), "tsqr_4096x32": lambda: tsqr_line("tsqr_4096x32")}[args.only]
         print(json.dumps({args.only: fn()}))
         return
     dev = torch.device("cuda:0")
@@ -515,29 +554,8 @@ def main():
     if not args.no_secondary:
         out["peaks_measured"] = measured_peaks(dev)
         sec = {}
-        for (m2, n2, key) in [(1 << 20, 64, "tsqr_1Mx64"), (4096, 32, "tsqr_4096x32")]:
-            B0 = caqr.fortran(inputs.gaussian(m2, n2, inputs.SEEDS[key]), device=dev)
-            B = torch.empty_like(B0.t()).t()
-            times = []
-            reps = 20 if m2 > 4096 else 50
-            for it in range(5 + reps):
-                B.copy_(B0)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                G = caqr.tsqr(B)
-                e1.record()
-                torch.cuda.synchronize()
-                if it >= 5:
-                    times.append(e0.elapsed_time(e1))
-                G.close()
-            t = float(np.median(times))
-            gbs = panel_bytes(m2, n2) / (t * 1e-3) / 1e9
-            sec[key] = {"median_us": round(t * 1e3, 2), "p10_us": round(float(np.percentile(times, 10)) * 1e3, 2),
-                        "p90_us": round(float(np.percentile(times, 90)) * 1e3, 2),
-                        "gflops": round((2.0 * m2 * n2 * n2 - 2.0 * n2 ** 3 / 3) / (t * 1e-3) / 1e9, 1),
-                        "algorithmic_GBps": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / PEAK_HBM_GBS, 2)}
-            del B0, B
+        for key in ("tsqr_1Mx64", "tsqr_4096x32"):
+            sec[key] = tsqr_line(key)
         sec["inner_block"] = inner_block_line(dev, n)
         # uneven batch (2000 problems, m log-uniform in [256, 65536], n in {8,16,32,64}),
         # plans from the autotuner; one step = one tsqr_factor_batched call
