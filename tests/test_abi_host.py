@@ -202,3 +202,14 @@ def test_inner_block_validation_without_device():
     inf = (caqr.LsInfo * 1)()
     o = caqr.TreeOpts(0, 0, 32, 0)
     assert lib.ls_solve_batched(None, 1, M, N, R, P, M, P, M, ctypes.byref(o), inf) == 4
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says why."""
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
