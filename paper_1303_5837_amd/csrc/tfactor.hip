@@ -4,7 +4,8 @@
 //
 // One workgroup per leaf or node, all in one launch.  G = Y^T Y is computed
 // on FP64 MFMA from 64-row chunks of the reflectors staged through LDS
-// (coalesced loads, double-buffered); its 16x16 blocks on and above the
+// (coalesced loads of every chunk issued at once, then two LDS buffers in
+// turn); its 16x16 blocks on and above the
 // diagonal are divided among the four waves, so each block is complete in one
 // wave.  T then follows from G and tau by the blocked recurrence.
 #include "device_common.hpp"
@@ -55,21 +56,26 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
     const double *tau = is_leaf ? f.tau_leaf : f.tau_node;
     sm.taus[tid] = (tid < f.b) ? tau[(int64_t)idx * kMaxB + tid] : 0.0;
   }
-  Stage st;
+  // every chunk's loads issued at once (one round trip instead of one per
+  // chunk); a leaf has at most four 64-row chunks
+  Stage st[4];
   if (is_leaf) {
-    stage_load<kLeafY>(st, f.Y, f.ldy, row0, row0, f.m, f.b, vec_ok, tid);
-    stage_fix<kLeafY>(st, 0, tid);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nch) stage_load<kLeafY>(st[c], f.Y, f.ldy, row0 + 64 * c, row0, f.m, f.b, vec_ok, tid);
+    stage_fix<kLeafY>(st[0], 0, tid);
   } else {
-    stage_load<kNodeV>(st, f.Y, f.ldy, row0, row0, f.m, f.b, vec_ok, tid);
-    stage_fix<kNodeV>(st, 0, tid);
+    stage_load<kNodeV>(st[0], f.Y, f.ldy, row0, row0, f.m, f.b, vec_ok, tid);
+    stage_fix<kNodeV>(st[0], 0, tid);
   }
-  stage_store(st, sm.buf[0], tid);
+  stage_store(st[0], sm.buf[0], tid);
   __syncthreads();
   f64x4 g[PW];
 #pragma unroll
   for (int q = 0; q < PW; ++q) g[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) stage_load<kLeafY>(st, f.Y, f.ldy, row0 + 64 * (c + 1), row0, f.m, f.b, vec_ok, tid);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= nch) break;
     const double *ys = sm.buf[c & 1];
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
@@ -87,7 +93,7 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
         for (int r = 0; r < 4; ++r) g[q] = mfma16x16x4(ya[r], yc[r], g[q]);
       }
     }
-    if (c + 1 < nch) stage_store(st, sm.buf[(c + 1) & 1], tid);
+    if (c + 1 < 4 && c + 1 < nch) stage_store(st[c + 1 < 4 ? c + 1 : 3], sm.buf[(c + 1) & 1], tid);
     __syncthreads();
   }
   // strictly upper G into buffer 0: register r of lane (li, lk) of pair (a, c)
