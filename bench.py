@@ -2,8 +2,8 @@
 """Benchmark of the multilevel QR path on one MI355X.
 
 Headline: CAQR FP64 GFLOP/s on an 8192 x 8192 N(0,1) matrix (seed 2), panel
-width 64, leaf rows 256, binary tree per panel (workgroup leaf, workgroup,
-device), flops counted as LAPACK's 4 n^3 / 3.  One step = one factorization
+width 64, leaf rows 256, binary tree per panel (one 256-row leaf per
+workgroup, then the device-wide levels), flops counted as LAPACK's 4 n^3 / 3.  One step = one factorization
 (every panel: leaf QR, reduction tree, trailing update).  A is restored from a
 pristine device copy before each step, outside the event-timed factorization.
 
@@ -522,7 +522,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"caqr_fp64_{n}x{n}_nb{nb}", "m": n, "n": n, "nb": nb, "leaf_rows": 256,
-                   "tree": "binary per panel: workgroup leaf, workgroup, device", "seed": inputs.SEEDS["caqr_8192sq"],
+                   "tree": "binary per panel: 256-row leaf per workgroup (leaves_per_wg 1), device-wide levels", "seed": inputs.SEEDS["caqr_8192sq"],
                    "flop_count": "LAPACK 4n^3/3"},
         "pct_fp64_peak": round(100.0 * gflops / (PEAK_FP64_TFLOPS * 1e3), 2),
         "gflops_executed": round(executed_flops(n, n, nb) / (ms * 1e-3) / 1e9, 2),

@@ -143,6 +143,16 @@ caqr_status_t caqr_get_stream(caqr_handle_t h, void **stream);
  * would exceed it returns CAQR_ERR_ALLOC without enqueuing anything. */
 caqr_status_t caqr_set_workspace_limit(caqr_handle_t h, size_t bytes);
 
+/* Host-forced failure, for tests of error propagation through the ABI: with
+ * k >= 1 the k-th library launch site this handle reaches from now on (a
+ * panel, T formation, a trailing update or Q application, a back
+ * substitution, a batched group) returns CAQR_ERR_DEVICE from the call that
+ * reached it instead of enqueuing its kernel, as an asynchronous device error
+ * would; the call releases what it allocated, and the handle stays usable.
+ * Work enqueued before that site runs normally.  k = 0 switches it off.
+ * Errors: CAQR_ERR_INVALID_VALUE for a NULL handle or k < 0. */
+caqr_status_t caqr_debug_fail_at(caqr_handle_t h, int64_t k);
+
 /* Wait for all work enqueued by this handle; report asynchronous errors. */
 caqr_status_t caqr_sync(caqr_handle_t h);
 
@@ -361,18 +371,28 @@ caqr_status_t caqr_server_create(const caqr_server_opts_t *o, caqr_server_t *S);
    lda) and m-by-nrhs B (ldb); the n-by-nrhs solution goes to X (ldx >= n).
    A, B and X are device memory owned by the caller: A and B are only read (the
    server works on copies) and must stay valid and unchanged, and X unused,
-   until caqr_server_wait returns for the ticket.  Returns at once.  Errors
-   (nothing is queued): CAQR_ERR_INVALID_VALUE for negative sizes, leading
-   dimensions below max(1, m) (max(1, n) for ldx), NULL pointers with nonzero
-   sizes, a NULL ticket or server; CAQR_ERR_NOT_SUPPORTED for m < n;
-   CAQR_ERR_ALLOC when the request's footprint exceeds the whole budget. */
+   until caqr_server_wait returns for the ticket.  Ordering: `stream` (a
+   hipStream_t passed as void*) is the caller's stream that produced A and B
+   and last used X; an event recorded on it at submit orders the request's
+   device work after everything enqueued there so far.  With stream == NULL
+   the caller guarantees that A, B and X are complete on the device (e.g. the
+   producing stream synchronized) before the call.  X is complete on the
+   device when caqr_server_wait returns.  Returns at once.  Errors (nothing is
+   queued): CAQR_ERR_INVALID_VALUE for negative sizes, leading dimensions
+   below max(1, m) (max(1, n) for ldx), NULL pointers with nonzero sizes, a
+   NULL ticket or server; CAQR_ERR_NOT_SUPPORTED for m < n; CAQR_ERR_ALLOC
+   when the request's footprint exceeds the whole budget; CAQR_ERR_DEVICE when
+   the ordering event cannot be recorded. */
 caqr_status_t caqr_server_submit(caqr_server_t S, int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
-                                 const double *B, int64_t ldb, double *X, int64_t ldx, int64_t *ticket);
+                                 const double *B, int64_t ldb, double *X, int64_t ldx, void *stream,
+                                 int64_t *ticket);
 
 /* Block until the request has finished; fill info (status, and the first
    zero pivot for CAQR_ERR_SINGULAR) and times (either may be NULL), and
    release the ticket.  Returns the request's status (as ls_solve would), or
-   CAQR_ERR_INVALID_VALUE for an unknown or already released ticket. */
+   CAQR_ERR_INVALID_VALUE for an unknown or already released ticket.  Only one
+   wait may claim a ticket: a second wait on the same ticket, concurrent or
+   later, returns CAQR_ERR_INVALID_VALUE and touches nothing. */
 caqr_status_t caqr_server_wait(caqr_server_t S, int64_t ticket, caqr_ls_info_t *info, caqr_request_times_t *times);
 
 /* Finish every queued request, stop the workers and free the server.

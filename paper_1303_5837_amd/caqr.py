@@ -86,6 +86,7 @@ EXPORTS = [
     "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_set_trace_kinds", "caqr_trace_read",
     "tsqr_factor_batched", "caqr_batch_destroy", "caqr_batch_get_plan", "caqr_batch_get_signs", "caqr_tune_batched",
     "caqr_batch_plan_for", "ls_solve_batched", "caqr_server_create", "caqr_server_submit", "caqr_server_wait", "caqr_server_destroy",
+    "caqr_debug_fail_at",
 ]
 
 
@@ -103,6 +104,7 @@ def _lib():
         L.caqr_set_stream.argtypes = [vp, vp]
         L.caqr_get_stream.argtypes = [vp, ctypes.POINTER(vp)]
         L.caqr_set_workspace_limit.argtypes = [vp, ctypes.c_size_t]
+        L.caqr_debug_fail_at.argtypes = [vp, i64]
         L.caqr_sync.argtypes = [vp]
         L.caqr_status_string.argtypes = [i32]
         L.caqr_status_string.restype = ctypes.c_char_p
@@ -128,7 +130,7 @@ def _lib():
         L.ls_solve_batched.argtypes = [vp, i64, pi64, pi64, pi64, ctypes.POINTER(vp), pi64, ctypes.POINTER(vp), pi64,
                                        ctypes.POINTER(TreeOpts), ctypes.POINTER(LsInfo)]
         L.caqr_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
-        L.caqr_server_submit.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(i64)]
+        L.caqr_server_submit.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.POINTER(i64)]
         L.caqr_server_wait.argtypes = [vp, i64, ctypes.POINTER(LsInfo), ctypes.POINTER(RequestTimes)]
         L.caqr_server_destroy.argtypes = [vp]
         for name in EXPORTS:
@@ -170,6 +172,11 @@ class Handle:
 
     def set_workspace_limit(self, nbytes: int):
         _check(_lib().caqr_set_workspace_limit(self._h, nbytes), "caqr_set_workspace_limit")
+
+    def fail_at(self, k: int):
+        """Test hook: the k-th library launch site from now on reports a device
+        error instead of enqueuing (0 switches it off)."""
+        _check(_lib().caqr_debug_fail_at(self._h, k), "caqr_debug_fail_at")
 
     def sync(self):
         _check(_lib().caqr_sync(self._h), "caqr_sync")
@@ -439,12 +446,15 @@ class Server:
 
     def submit(self, A: torch.Tensor, B: torch.Tensor, X: torch.Tensor) -> int:
         """Queue min ||A X - B|| (A, B read only; X receives the n-by-nrhs
-        solution).  The tensors are kept alive until ``wait``."""
+        solution).  The request's device work is ordered after what torch's
+        current stream has enqueued so far (A, B and X as that stream sees
+        them).  The tensors are kept alive until ``wait``."""
         m, n = A.shape
         t = ctypes.c_int64()
+        stream = torch.cuda.current_stream(A.device).cuda_stream
         _check(_lib().caqr_server_submit(self._s, m, n, B.shape[1], ctypes.c_void_p(A.data_ptr()), _ld(A),
                                          ctypes.c_void_p(B.data_ptr()), _ld(B), ctypes.c_void_p(X.data_ptr()),
-                                         _ld(X), ctypes.byref(t)), "caqr_server_submit")
+                                         _ld(X), ctypes.c_void_p(stream), ctypes.byref(t)), "caqr_server_submit")
         self._keep[t.value] = (A, B, X)
         return t.value
 

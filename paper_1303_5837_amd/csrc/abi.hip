@@ -75,6 +75,7 @@ struct caqr_handle_s {
   // (CAQR_F64, CAQR_F32): [n bucket 8/16/32/64][log2 m - 8]
   bool tuned[2] = {false, false};
   caqr_tree_opts_t tuned_plan[2][4][9] = {};
+  int64_t fault_countdown = 0;  // caqr_debug_fail_at: launch sites left before a forced error (0: off)
 };
 
 struct caqr_batch_s {
@@ -127,6 +128,13 @@ struct caqr_factors_s {
 namespace {
 
 caqr_status_t to_status(hipError_t e) { return e == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE; }
+
+// Host-forced failure for tests of error propagation: after caqr_debug_fail_at(h, k)
+// the k-th launch site reached reports a device error instead of enqueuing.
+bool forced_fault(caqr_handle_t h) {
+  if (h->fault_countdown <= 0) return false;
+  return --h->fault_countdown == 0;
+}
 
 hipEvent_t pool_event(caqr_handle_t h) {
   if (!h->event_pool.empty()) {
@@ -361,6 +369,7 @@ caqr_status_t launch_panel_t(caqr_handle_t h, caqr_factors_t F, int idx, hipStre
   f.tau_node = p.tau_node;
   f.T_leaf = p.T_leaf;
   f.T_node = p.T_node;
+  if (forced_fault(h)) return CAQR_ERR_DEVICE;
   TraceScope ts(h, CAQR_TRACE_FORM_T, idx, p.m, p.b, p.b, p.L, st);
   return launch_form_t(f, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
 }
@@ -379,6 +388,7 @@ caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form
   const PanelRec &p = F->panels[idx];
   PanelParams pp = panel_params(h, F, p);
   const bool levels = ceil_div(p.L, F->lpw) >= kLevelLaunchWgs;
+  if (forced_fault(h)) return CAQR_ERR_DEVICE;
   {
     TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
     if (levels) pp.tickets = nullptr;
@@ -398,6 +408,7 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
   if (st == h->stream && p.L < kLevelLaunchWgs) u.tickets = panel_tickets(h);
   // the same test launch_apply_qt makes: one tree-climbing launch, or levels
   const bool one_launch = u.tickets && u.tiles <= kTreeTiles && u.L > 1;
+  if (forced_fault(h)) return CAQR_ERR_DEVICE;
   TraceScope ts(h, one_launch ? CAQR_TRACE_UPDATE_T : CAQR_TRACE_UPDATE_T_LEVELS, idx, p.m, k, p.b, p.L, st);
   return launch_apply_qt(u, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
 }
@@ -701,6 +712,7 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
 caqr_status_t batch_launch(caqr_handle_t h, caqr_batch_t B) {
   for (size_t gi = 0; gi < B->groups.size(); ++gi) {
     const auto &g = B->groups[gi];
+    if (forced_fault(h)) return CAQR_ERR_DEVICE;
     TraceScope ts(h, CAQR_TRACE_PANEL, (int)gi, g.rows, 16 * g.nq, g.leaf_rows, (int)std::min<int64_t>(g.leaves, INT32_MAX));
     const hipError_t e =
         B->dt == CAQR_F32
@@ -831,6 +843,12 @@ caqr_status_t caqr_get_stream(caqr_handle_t h, void **stream) {
   return CAQR_SUCCESS;
 }
 
+caqr_status_t caqr_debug_fail_at(caqr_handle_t h, int64_t k) {
+  if (!h || k < 0) return CAQR_ERR_INVALID_VALUE;
+  h->fault_countdown = k;
+  return CAQR_SUCCESS;
+}
+
 caqr_status_t caqr_set_workspace_limit(caqr_handle_t h, size_t bytes) {
   if (!h) return CAQR_ERR_INVALID_VALUE;
   h->ws_limit = bytes;
@@ -872,12 +890,14 @@ caqr_status_t apply_q(caqr_handle_t h, caqr_factors_t F, caqr_op_t op, int64_t k
   if (op == CAQR_OP_T) {
     for (auto &p : F->panels) {
       UpdateParams u = update_params(h, F, p, C, ldc, k);
+      if (forced_fault(h)) return CAQR_ERR_DEVICE;
       TraceScope ts(h, CAQR_TRACE_UPDATE_T, (int)(&p - &F->panels[0]), p.m, k, p.b, p.L);
       if (launch_apply_qt(u, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
     }
   } else {
     for (auto it = F->panels.rbegin(); it != F->panels.rend(); ++it) {
       UpdateParams u = update_params(h, F, *it, C, ldc, k);
+      if (forced_fault(h)) return CAQR_ERR_DEVICE;
       TraceScope ts(h, CAQR_TRACE_UPDATE_N, (int)(&*it - &F->panels[0]), it->m, k, it->b, it->L);
       if (launch_apply_qn(u, h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
     }
@@ -947,7 +967,8 @@ caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, doub
 namespace caqr {
 
 // The plan of a least-squares solve depends only on (m, n): TSQR (leaf 256,
-// four leaves per workgroup) for n <= 64, else CAQR with 64-column panels.
+// one leaf per workgroup, the library defaults) for n <= 64, else CAQR with
+// 64-column panels.
 size_t ls_workspace_bytes(int64_t m, int64_t n) {
   if (n <= 0) return 0;
   return factor_ws_bytes(m, n, n <= kNbMax ? std::max<int64_t>(n, 1) : kNbMax, 256, nullptr);
@@ -973,6 +994,7 @@ caqr_status_t ls_solve_ws(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, d
                                    : factor_impl(h, m, n, kNbMax, A, lda, nullptr, &F, false, ws);
   if (st) return st;
   st = apply_q(h, F, CAQR_OP_T, nrhs, B, ldb);
+  if (!st && forced_fault(h)) st = CAQR_ERR_DEVICE;
   if (!st && launch_trsm_upper(A, lda, n, B, ldb, nrhs, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
   if (!st && launch_check_solution(A, lda, n, B, ldb, nrhs, h->status_dev, h->stream) != hipSuccess)
     st = CAQR_ERR_DEVICE;

@@ -94,9 +94,11 @@ struct Request {
   int64_t ldx = 0;
   size_t a_bytes = 0, b_bytes = 0, bytes = 0, off = 0;
   caqr_request_times_t t{};
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit, or null
   caqr_status_t status = CAQR_SUCCESS;
   int64_t index = 0;
   bool done = false;
+  bool claimed = false;  // a caqr_server_wait owns the ticket
 };
 
 caqr_status_t check_request(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
@@ -142,7 +144,10 @@ struct caqr_server_s {
     void *ws = base + r->a_bytes + r->b_bytes;
     const size_t col = (size_t)r->m * sizeof(double);
     caqr_status_t st = CAQR_SUCCESS;
-    if (r->n > 0 && r->nrhs > 0) {
+    // A and B (and any earlier use of X) are ordered before the copies by the
+    // event the caller's stream recorded at submit
+    if (r->ready && hipStreamWaitEvent(s, r->ready, 0) != hipSuccess) st = CAQR_ERR_DEVICE;
+    if (!st && r->n > 0 && r->nrhs > 0) {
       if (hipMemcpy2DAsync(Aw, col, r->A, (size_t)r->lda * sizeof(double), col, (size_t)r->n, hipMemcpyDeviceToDevice,
                            s) != hipSuccess ||
           hipMemcpy2DAsync(Bw, col, r->B, (size_t)r->ldb * sizeof(double), col, (size_t)r->nrhs,
@@ -158,6 +163,12 @@ struct caqr_server_s {
             hipStreamSynchronize(s) != hipSuccess)
           st = CAQR_ERR_DEVICE;
       }
+    } else if (!st && r->ready && hipStreamSynchronize(s) != hipSuccess) {
+      st = CAQR_ERR_DEVICE;
+    }
+    if (r->ready) {
+      (void)hipEventDestroy(r->ready);
+      r->ready = nullptr;
     }
     r->status = st;
   }
@@ -232,7 +243,8 @@ caqr_status_t caqr_server_create(const caqr_server_opts_t *o, caqr_server_t *S) 
 }
 
 caqr_status_t caqr_server_submit(caqr_server_t S, int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
-                                 const double *B, int64_t ldb, double *X, int64_t ldx, int64_t *ticket) {
+                                 const double *B, int64_t ldb, double *X, int64_t ldx, void *stream,
+                                 int64_t *ticket) {
   if (!ticket) return CAQR_ERR_INVALID_VALUE;
   caqr_status_t st = check_request(m, n, nrhs, A, lda, B, ldb, X, ldx);
   if (st) return st;
@@ -259,9 +271,23 @@ caqr_status_t caqr_server_submit(caqr_server_t S, int64_t m, int64_t n, int64_t 
     delete r;
     return CAQR_ERR_ALLOC;
   }
+  if (stream) {
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(S->device);
+    const bool ok = hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) == hipSuccess &&
+                    hipEventRecord(r->ready, (hipStream_t)stream) == hipSuccess;
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (!ok) {
+      if (r->ready) (void)hipEventDestroy(r->ready);
+      delete r;
+      return CAQR_ERR_DEVICE;
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) {
+      if (r->ready) (void)hipEventDestroy(r->ready);
       delete r;
       return CAQR_ERR_INVALID_VALUE;
     }
@@ -278,10 +304,12 @@ caqr_status_t caqr_server_wait(caqr_server_t S, int64_t ticket, caqr_ls_info_t *
   if (!S) return CAQR_ERR_INVALID_VALUE;
   std::unique_lock<std::mutex> lk(S->mu);
   auto it = S->reqs.find(ticket);
-  if (it == S->reqs.end()) return CAQR_ERR_INVALID_VALUE;
+  // unknown, released, or already claimed by another waiting thread
+  if (it == S->reqs.end() || it->second->claimed) return CAQR_ERR_INVALID_VALUE;
   Request *r = it->second;
+  r->claimed = true;  // no other wait touches r from here on
   S->cv_done.wait(lk, [&] { return r->done; });
-  S->reqs.erase(it);
+  S->reqs.erase(ticket);  // looked up again: the map may have changed while waiting
   lk.unlock();
   const caqr_status_t st = r->status;
   if (info) {
@@ -308,7 +336,10 @@ caqr_status_t caqr_server_destroy(caqr_server_t S) {
   for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
   if (S->slab) (void)hipFree(S->slab);
   if (prev >= 0) (void)hipSetDevice(prev);
-  for (auto &kv : S->reqs) delete kv.second;
+  for (auto &kv : S->reqs) {
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+    delete kv.second;
+  }
   delete S;
   return CAQR_SUCCESS;
 }

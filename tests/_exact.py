@@ -99,3 +99,22 @@ def signed_permutation_case(m: int, n: int, seed: int = 0):
     X[:n] = R0
     X *= rng.choice([-1.0, 1.0], size=(m, 1))
     return np.asfortranarray(X[rng.permutation(m)]), R0
+
+
+def exact_eta(A: np.ndarray, x: np.ndarray, b: np.ndarray, dps: int = 60) -> float:
+    """eta(x) = ||A^T (b - A x)||_2 / (||A||_2 (||A||_2 ||x||_2 + ||b||_2)) with the
+    residual and A^T r exact in rationals, and the 2-norms (||A||_2 as the square
+    root of the largest eigenvalue of the exact A^T A) at `dps` digits."""
+    m, n = A.shape
+    Af = [[Fraction(float(A[i, j])) for j in range(n)] for i in range(m)]
+    xf = [Fraction(float(v)) for v in np.ravel(x)]
+    bf = [Fraction(float(v)) for v in np.ravel(b)]
+    r = [bf[i] - sum((Af[i][j] * xf[j] for j in range(n)), Fraction(0)) for i in range(m)]
+    g = [sum((Af[i][j] * r[i] for i in range(m)), Fraction(0)) for j in range(n)]
+    G = exact_gram(A)
+    with mpmath.workdps(dps):
+        mp = lambda q: mpmath.mpf(q.numerator) / q.denominator
+        nrm = lambda v: mpmath.sqrt(mp(sum((q * q for q in v), Fraction(0))))
+        ev = mpmath.eigsy(mpmath.matrix([[mp(q) for q in row] for row in G]), eigvals_only=True)
+        na = mpmath.sqrt(max(ev[i] for i in range(n)))
+        return float(nrm(g) / (na * (na * nrm(xf) + nrm(bf))))

@@ -159,4 +159,31 @@ def pin_ls(lib):
     return _res(True, "ok")
 
 
-ALL_PINS = [pin_bruteforce, pin_closed_forms, pin_upper_triangular, pin_dyadic, pin_lapack, pin_invariants, pin_ls]
+def pin_ls_eta(lib, eta=None):
+    """The least-squares backward-error measure against its definition evaluated
+    exactly: residual and A^T r in rationals, 2-norms and ||A||_2 (largest
+    singular value, from the exact Gram matrix) at 60 digits.  Inconsistent
+    systems (b not in the range of A) at points x away from the solution, where
+    A^T r is far from zero, and near it (x = x* + a small perturbation), where
+    it is small but not zero; ||A||_2 computed by the function and passed in."""
+    eta = oracle.ls_eta if eta is None else eta
+    rng = np.random.default_rng(17)
+    for (m, n, scale) in [(7, 3, 1.0), (12, 5, 1e-3), (20, 4, 1.0), (9, 1, 1.0), (15, 6, 1e-8)]:
+        A = rng.standard_normal((m, n))
+        b = rng.standard_normal(m)  # almost surely not in the range of A
+        xs = _exact.exact_ls(A, b)
+        for x in (xs + scale * rng.standard_normal(n), rng.standard_normal(n)):
+            ref = _exact.exact_eta(A, x, b)
+            for norm_a in (None, float(np.linalg.norm(A, 2))):
+                got = eta(A, x, b, norm_a=norm_a)
+                # FP64 evaluation: the residual's rounding (about u ||b||) relative
+                # to ||A^T r|| bounds the error of the numerator
+                tol = 1e-12 * ref + 64 * U * np.linalg.norm(A, 2) * np.linalg.norm(b) / (
+                    np.linalg.norm(A, 2) * (np.linalg.norm(A, 2) * np.linalg.norm(x) + np.linalg.norm(b)))
+                if not abs(got - ref) <= tol:
+                    return _res(False, f"m={m} n={n} eta={got!r} exact={ref!r}")
+    return _res(True, "ok")
+
+
+ALL_PINS = [pin_bruteforce, pin_closed_forms, pin_upper_triangular, pin_dyadic, pin_lapack, pin_invariants, pin_ls,
+            pin_ls_eta]

@@ -139,12 +139,13 @@ def test_server_argument_validation_without_device():
     p = ctypes.c_void_p(0x1000)
     t = ctypes.c_int64()
     sub = lib.caqr_server_submit
-    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 10, ctypes.byref(t)) == 1   # valid request, NULL server
-    assert sub(None, 100, 10, 1, p, 99, p, 100, p, 10, ctypes.byref(t)) == 1    # lda < m
-    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 9, ctypes.byref(t)) == 1    # ldx < n
-    assert sub(None, 100, 10, 1, None, 100, p, 100, p, 10, ctypes.byref(t)) == 1  # NULL A
-    assert sub(None, 10, 20, 1, p, 10, p, 10, p, 20, ctypes.byref(t)) == 4      # m < n
-    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 10, None) == 1              # NULL ticket
+    st = ctypes.c_void_p(0)  # no ordering stream
+    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 10, st, ctypes.byref(t)) == 1   # valid request, NULL server
+    assert sub(None, 100, 10, 1, p, 99, p, 100, p, 10, st, ctypes.byref(t)) == 1    # lda < m
+    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 9, st, ctypes.byref(t)) == 1    # ldx < n
+    assert sub(None, 100, 10, 1, None, 100, p, 100, p, 10, st, ctypes.byref(t)) == 1  # NULL A
+    assert sub(None, 10, 20, 1, p, 10, p, 10, p, 20, st, ctypes.byref(t)) == 4      # m < n
+    assert sub(None, 100, 10, 1, p, 100, p, 100, p, 10, st, None) == 1              # NULL ticket
     assert lib.caqr_server_wait(None, 1, None, None) == 1
     assert lib.caqr_server_destroy(None) == 1
 

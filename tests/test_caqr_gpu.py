@@ -3,9 +3,10 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
-from paper_1303_5837_amd import inputs
+from paper_1303_5837_amd import caqr, inputs
 from tests._gpu import banner, caqr_gpu, factored, q_thin, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -55,21 +56,64 @@ def test_determinism():
     assert np.array_equal(factored(caqr_gpu(A)[0]), a)
 
 
-def test_square_8192_sampled():
-    """The square configuration at full size: sampled entries of R against stored
-    oracle values (tests/golden/make_golden.py, oracle only) and the Gram identity
+# Panels of 128 or more workgroups (m_s >= 128 leaves of 256 rows) finish their
+# trees with one launch per level, and the next panel's columns are updated
+# level by level too: the path of the tall least-squares shapes.
+TALL = [(40000, 200), (65536, 1024)]
+
+
+@pytest.mark.parametrize("m,n", TALL)
+def test_tall_caqr_level_path(m, n):
+    """R against the oracle, Q_thin^T C (unique for full-rank A) against the
+    oracle's, the round trip Q (Q^T C) = C, and Q^T A = [R; 0]."""
+    require_gpu()
+    banner(f"tall caqr parity m={m} n={n}")
+    A = inputs.gaussian(m, n, 2100 + n)
+    dA0 = caqr.fortran(A)
+    F, R = caqr_gpu(A)
+    assert F.info().leaves_panel0 >= 128
+    oracle.set_threads(16)
+    f = oracle.qr(A)
+    assert np.all(np.diag(R) >= 0)
+    assert oracle.rel_fro(R, f.R) <= TOL_R
+    C = inputs.gaussian(m, 8, 2200 + n)
+    dC = caqr.fortran(C)
+    F.apply_q(dC, caqr.OP_T)
+    torch.cuda.synchronize()
+    QtC = dC.cpu().numpy()
+    assert oracle.rel_fro(QtC[:n], f.apply_qt(C)[:n]) <= TOL_R
+    F.apply_q(dC, caqr.OP_N)
+    torch.cuda.synchronize()
+    assert oracle.rel_fro(dC.cpu().numpy(), C) <= 1e-14
+    F.apply_q(dA0, caqr.OP_T)  # Q^T A: R on top, zero below
+    torch.cuda.synchronize()
+    QtA = dA0.cpu().numpy()
+    nrm = np.linalg.norm(A)
+    assert np.linalg.norm(QtA[:n] - R) / nrm <= 1e-13
+    assert np.linalg.norm(QtA[n:]) / nrm <= 1e-13
+
+
+def test_square_8192_full():
+    """The square configuration at full size: every entry of R against the
+    oracle run in the test, plus the stored oracle sample
+    (tests/golden/make_golden.py, oracle only) and the Gram identity
     R^T R = A^T A on sampled entries."""
     require_gpu()
-    banner("caqr 8192x8192 full-size sampled parity")
-    path = os.path.join(GOLDEN, "caqr_8192_r_sample.npz")
-    g = np.load(path)
+    banner("caqr 8192x8192 full-size parity (oracle in the test)")
     A = inputs.gaussian(8192, 8192, inputs.SEEDS["caqr_8192sq"])
     F, R = caqr_gpu(A)
+    del F
+    oracle.set_threads(16)
+    Rref = oracle.qr_r(A)
+    assert np.all(np.diag(R) >= 0)
+    assert oracle.rel_fro(R, Rref) <= TOL_R
+    col = np.linalg.norm(R - Rref, axis=0) / np.linalg.norm(Rref, axis=0)
+    banner(f"  normwise {oracle.rel_fro(R, Rref):.2e}, worst column {col.max():.2e}")
+    assert col.max() <= TOL_R
+    g = np.load(os.path.join(GOLDEN, "caqr_8192_r_sample.npz"))
     ii, jj, ref = g["i"], g["j"], g["r"]
-    got = R[ii, jj]
-    scale = np.linalg.norm(g["diag"])
-    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL_R
-    assert np.linalg.norm(np.diag(R) - g["diag"]) / scale <= TOL_R
+    assert np.linalg.norm(R[ii, jj] - ref) / np.linalg.norm(ref) <= TOL_R
+    assert np.linalg.norm(np.diag(R) - g["diag"]) / np.linalg.norm(g["diag"]) <= TOL_R
     rng = np.random.default_rng(93)
     pi = rng.integers(0, 8192, 200)
     pj = rng.integers(0, 8192, 200)

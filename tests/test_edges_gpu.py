@@ -74,8 +74,10 @@ def test_square_and_one_by_one():
     X, info = caqr.ls_solve(caqr.fortran(A), caqr.fortran(b))
     torch.cuda.synchronize()
     assert info.status == 0
-    x_ref = np.linalg.solve(A, b)
+    x_ref, st = oracle.ls(A, b)
+    assert st == 0
     assert np.linalg.norm(X.cpu().numpy() - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
+    assert oracle.ls_eta(A, X.cpu().numpy(), b) <= 1e-15
     for v in (-3.0, 0.0, 2.5):
         F, R = caqr_gpu(np.array([[v]]), nb=64)
         assert R[0, 0] == abs(v) and F.signs()[0] == (-1.0 if v < 0 else 1.0)

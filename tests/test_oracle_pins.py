@@ -5,6 +5,7 @@ Every pin in ``_pins`` must pass on the oracle, and every planted mistake
 """
 import os
 
+import numpy as np
 import pytest
 
 import oracle
@@ -40,3 +41,43 @@ def test_planted_mistake_is_caught(k, tmp_path):
         if not ok:
             failed.append(pin.__name__)
     assert failed, f"mutant {k} ({MUTANTS[k]}) passed every pin"
+
+
+def _eta_parts(A, x, b, norm_a=None):
+    A = np.asarray(A, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64).reshape(A.shape[1], -1)
+    b = np.asarray(b, dtype=np.float64).reshape(A.shape[0], -1)
+    na = float(np.linalg.norm(A, 2)) if norm_a is None else norm_a
+    return A, x, b, na, b - A @ x
+
+
+def _eta_no_at(A, x, b, norm_a=None):  # A^T dropped from the numerator
+    A, x, b, na, r = _eta_parts(A, x, b, norm_a)
+    return float(np.max(np.linalg.norm(r, axis=0) / (na * (na * np.linalg.norm(x, axis=0) + np.linalg.norm(b, axis=0)))))
+
+
+def _eta_one_norm_a(A, x, b, norm_a=None):  # ||A|| once instead of twice in front of ||x||
+    A, x, b, na, r = _eta_parts(A, x, b, norm_a)
+    return float(np.max(np.linalg.norm(A.T @ r, axis=0) / (na * (np.linalg.norm(x, axis=0) + np.linalg.norm(b, axis=0)))))
+
+
+def _eta_no_b(A, x, b, norm_a=None):  # ||b|| dropped from the denominator
+    A, x, b, na, r = _eta_parts(A, x, b, norm_a)
+    return float(np.max(np.linalg.norm(A.T @ r, axis=0) / (na * na * np.linalg.norm(x, axis=0))))
+
+
+def _eta_frobenius(A, x, b, norm_a=None):  # Frobenius norm of A in place of the 2-norm
+    A, x, b, _, r = _eta_parts(A, x, b, None)
+    na = float(np.linalg.norm(A)) if norm_a is None else norm_a
+    return float(np.max(np.linalg.norm(A.T @ r, axis=0) / (na * (na * np.linalg.norm(x, axis=0) + np.linalg.norm(b, axis=0)))))
+
+
+ETA_MUTANTS = {"drop A^T": _eta_no_at, "one factor ||A||": _eta_one_norm_a, "drop ||b||": _eta_no_b,
+               "Frobenius norm": _eta_frobenius}
+
+
+@pytest.mark.parametrize("name", sorted(ETA_MUTANTS))
+def test_planted_eta_mistake_is_caught(name, oracle_mod):
+    """Each planted mistake in the backward-error measure fails its pin."""
+    ok, _ = _pins.pin_ls_eta(oracle.LIB, eta=ETA_MUTANTS[name])
+    assert not ok, f"eta mutant '{name}' passed the pin"

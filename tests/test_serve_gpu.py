@@ -70,16 +70,44 @@ def test_served_equals_plain_bitwise():
     S2.close()
 
 
-def test_served_backward_error():
+U = 2.0 ** -53
+
+
+def ls_forward_bound(A, x, b):
+    """Relative distance allowed between two backward-stable least-squares
+    solutions (each within a relative backward error eps = 10 n u of the data):
+    twice the first-order perturbation bound
+    eps kappa (2 + (kappa + 1) ||r|| / (||A|| ||x||)), floored at 1e-11."""
+    s = np.linalg.svd(A, compute_uv=False)
+    kappa = s[0] / s[-1]
+    eps = 10 * A.shape[1] * U
+    r = b - A @ x
+    nr = np.linalg.norm(r, axis=0).max()
+    bound = eps * kappa * (2 + (kappa + 1) * nr / (s[0] * np.linalg.norm(x)))
+    return max(1e-11, 2 * bound), kappa
+
+
+def test_served_against_oracle():
+    """Every served solution against the oracle's least squares (within the
+    perturbation bound of the problem's conditioning, 1e-11 for the
+    well-conditioned ones) and within eta <= 1e-12 (the pinned backward-error
+    measure)."""
     require_gpu()
-    probs = problems(MIX[:6], 7200)
+    oracle.set_threads(16)
+    probs = problems(MIX, 7200)
     S = caqr.Server(workers=3, budget_bytes=1 << 30)
     got, res = serve(S, probs)
     for i, (A, B) in enumerate(probs):
         assert res[i][0] == 0
         Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+        Xref, st = oracle.ls(Ah, Bh)
+        assert st == 0
+        tol, kappa = ls_forward_bound(Ah, Xref, Bh)
+        err = oracle.rel_fro(got[i], Xref)
         eta = oracle.ls_eta(Ah, got[i], Bh)
-        banner(f"served {i}: eta {eta:.2e}")
+        banner(f"served {i}: m={Ah.shape[0]} n={Ah.shape[1]} kappa {kappa:.1e}: vs oracle {err:.2e} "
+               f"(bound {tol:.1e}), eta {eta:.2e}")
+        assert err <= tol
         assert eta <= 1e-12
     S.close()
 
