@@ -211,6 +211,24 @@ caqr_status_t caqr_factors_get_signs(caqr_handle_t h, caqr_factors_t F, double *
 caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
                        int64_t ldb, const caqr_ls_opts_t *o, caqr_ls_info_t *info);
 
+/* The solve of ls_solve without any device allocation, for callers that
+ * cannot allocate (code running under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, results, statuses and the
+ * waiting behaviour are those of ls_solve (no options).  The factors'
+ * tau/D/T workspace, the ticket counters of the reduction trees and the
+ * status words come from one static device array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends (resolved per device
+ * by caqr_create); the panel loop runs on the handle's stream alone (no
+ * second stream), and the ticket counters are cleared by a kernel at the
+ * start of every call.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (from several handles or threads) race and must be
+ * serialized by the caller.  Problems whose workspace does not fit return
+ * CAQR_ERR_NOT_SUPPORTED before anything is enqueued: about
+ * 64 * ceil(m / 256) KiB for n <= 64 (m up to about 250,000 rows), and about
+ * 128 * ceil(m_s / 256) KiB per 64-column panel beyond. */
+caqr_status_t ls_solve_noalloc(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
+                               double *B, int64_t ldb, caqr_ls_info_t *info);
+
 /* ------------------------------------------------------------- tracing */
 
 /* Per-launch device timing (HIP events recorded on the handle's stream around

@@ -86,7 +86,7 @@ EXPORTS = [
     "caqr_factors_get_info", "caqr_factors_get_signs", "ls_solve", "caqr_set_trace", "caqr_set_trace_kinds", "caqr_trace_read",
     "tsqr_factor_batched", "caqr_batch_destroy", "caqr_batch_get_plan", "caqr_batch_get_signs", "caqr_tune_batched",
     "caqr_batch_plan_for", "ls_solve_batched", "caqr_server_create", "caqr_server_submit", "caqr_server_wait", "caqr_server_destroy",
-    "caqr_debug_fail_at",
+    "caqr_debug_fail_at", "ls_solve_noalloc",
 ]
 
 
@@ -116,6 +116,7 @@ def _lib():
         L.caqr_factors_get_info.argtypes = [vp, ctypes.POINTER(FactorsInfo)]
         L.caqr_factors_get_signs.argtypes = [vp, vp, dp]
         L.ls_solve.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(LsOpts), ctypes.POINTER(LsInfo)]
+        L.ls_solve_noalloc.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, ctypes.POINTER(LsInfo)]
         L.caqr_set_trace.argtypes = [vp, i32]
         L.caqr_set_trace_kinds.argtypes = [vp, ctypes.c_uint32]
         L.caqr_trace_read.argtypes = [vp, ctypes.POINTER(TraceEntry), i64, ctypes.POINTER(i64)]
@@ -334,6 +335,21 @@ def ls_solve(A: torch.Tensor, B: torch.Tensor, device: int = 0):
                            ctypes.c_void_p(B.data_ptr()), _ld(B), None, ctypes.byref(info))
     if code not in (0, 5, 6):
         _check(code, "ls_solve")
+    return B[:n], info
+
+
+def ls_solve_noalloc(A: torch.Tensor, B: torch.Tensor, device: int = 0):
+    """ls_solve through the entry point that allocates no device memory (its
+    workspace is the library's static per-GPU scratch array): returns
+    (X = B[:n], info); raises CaqrError(CAQR_ERR_NOT_SUPPORTED) when the
+    problem's workspace does not fit that array."""
+    h = handle(device)
+    m, n = A.shape
+    info = LsInfo()
+    code = _lib().ls_solve_noalloc(h.ptr, m, n, B.shape[1], ctypes.c_void_p(A.data_ptr()), _ld(A),
+                                   ctypes.c_void_p(B.data_ptr()), _ld(B), ctypes.byref(info))
+    if code not in (0, 5, 6):
+        _check(code, "ls_solve_noalloc")
     return B[:n], info
 
 

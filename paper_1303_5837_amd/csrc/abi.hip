@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -50,6 +51,42 @@ struct PanelRec {
 };
 
 int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Device memory of ls_solve_noalloc, for callers that cannot allocate: the
+// factors' tau/D/T workspace, the ticket counters of the trees and the two
+// status words of one solve.  Every GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address: init_scratch resolves each device's copy once (hipGetSymbolAddress
+// with that device current) and every later use goes through that pointer.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve the calling thread's current device's copy of `scratch` (the
+// device is `device`); idempotent.
+bool init_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return true;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return false;
+  g_scratch_ptr[device] = ptr;
+  return true;
+}
+
+void *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -123,6 +160,8 @@ struct caqr_factors_s {
   bool t_formed = false;
   bool borrowed = false;    // small/tbuf lent by the caller (a served solve): not freed here
   size_t limit = 0;
+  unsigned *tickets = nullptr;  // lent ticket counters (zero on entry), else the handle's
+  bool lookahead = true;        // false: the panel loop on the handle's stream alone
 };
 
 namespace {
@@ -308,6 +347,14 @@ caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, do
   return CAQR_SUCCESS;
 }
 
+// Ticket counters a factorization uses: the panel trees, and the tile trees of
+// the next panel's update.
+size_t factor_tickets(caqr_factors_t F) {
+  size_t need = 0;
+  for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L * kTreeTiles);
+  return need;
+}
+
 PanelParams panel_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p) {
   PanelParams pp;
   pp.A = F->A + p.row0 + p.col0 * F->lda;
@@ -319,7 +366,7 @@ PanelParams panel_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p) {
   pp.tau_leaf = p.tau_leaf;
   pp.tau_node = p.tau_node;
   pp.d = p.d;
-  pp.tickets = panel_tickets(h);
+  pp.tickets = F->tickets ? F->tickets : panel_tickets(h);
   return pp;
 }
 
@@ -405,7 +452,7 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
   UpdateParams u = update_params(h, F, p, F->A + c0 * F->lda, F->lda, k);
   // the tickets belong to the handle's stream (panel kernels use them too);
   // tall panels update level by level instead (as their trees are built)
-  if (st == h->stream && p.L < kLevelLaunchWgs) u.tickets = panel_tickets(h);
+  if (st == h->stream && p.L < kLevelLaunchWgs) u.tickets = F->tickets ? F->tickets : panel_tickets(h);
   // the same test launch_apply_qt makes: one tree-climbing launch, or levels
   const bool one_launch = u.tickets && u.tiles <= kTreeTiles && u.L > 1;
   if (forced_fault(h)) return CAQR_ERR_DEVICE;
@@ -414,7 +461,10 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
 }
 
 // Factor every panel in order, updating the trailing matrix after each one
-// (the panel loop of Algorithm 1).  With more than one panel the loop looks
+// (the panel loop of Algorithm 1).  Without look-ahead (a single panel, or a
+// factorization that may use the handle's stream only) each panel's update
+// covers the whole trailing matrix and the next panel follows it.  With more
+// than one panel the loop looks
 // ahead: the next panel's columns are updated first, then the next panel is
 // factored on the handle's stream while the rest of the trailing matrix is
 // updated on a second stream; the next panel's own update waits for that.
@@ -423,12 +473,10 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
 // launch is ordered by stream order or by an event, and all work ends on the
 // handle's stream.
 caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) {
-  size_t need = 0;  // panel trees, and the tile trees of the next panel's update
-  for (auto &p : F->panels) need = std::max<size_t>(need, (size_t)p.L * kTreeTiles);
-  caqr_status_t st = ensure_tickets(h, need);
-  if (st) return st;
+  caqr_status_t st = CAQR_SUCCESS;
+  if (!F->tickets && (st = ensure_tickets(h, factor_tickets(F)))) return st;
   const int P = (int)F->panels.size();
-  const bool ahead = P > 1;
+  const bool ahead = P > 1 && F->lookahead;
   if (ahead && (st = ensure_side(h))) return st;
   if ((st = launch_panel(h, F, 0, form_t, h->stream))) return st;
   for (int idx = 0; idx < P; ++idx) {
@@ -436,8 +484,9 @@ caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) 
     const int64_t c0 = p.col0 + p.b;
     const int64_t k = F->n - c0;
     if (k <= 0) break;
-    if (!ahead || idx + 1 >= P) {
+    if (!ahead || idx + 1 >= P) {  // the whole trailing matrix, then the next panel
       if ((st = launch_trailing(h, F, idx, c0, k, h->stream))) return st;
+      if (idx + 1 < P && (st = launch_panel(h, F, idx + 1, form_t, h->stream))) return st;
       continue;
     }
     const int64_t kn = F->panels[idx + 1].b;  // columns of the next panel
@@ -502,7 +551,8 @@ caqr_status_t check_opts(const caqr_tree_opts_t *o) {
 }
 
 caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
-                          const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr, void *ws = nullptr) {
+                          const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr, void *ws = nullptr,
+                          unsigned *tickets = nullptr) {
   const int hr = resolve_leaf_rows(opts);
   // default: one leaf per workgroup (every leaf factored in parallel)
   const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : 1;
@@ -511,6 +561,10 @@ caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, dou
   caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, ws, &f);
   if (st) return st;
   f->inner_block = (opts && opts->inner_block < kNbMax) ? opts->inner_block : 0;
+  if (tickets) {  // lent counters: no allocation and no second stream
+    f->tickets = tickets;
+    f->lookahead = false;
+  }
   if (n > 0) {
     st = run_factorization(h, f, !tsqr);
     if (st) {
@@ -769,6 +823,10 @@ caqr_status_t caqr_create(caqr_handle_t *h, int device) {
   if (!p) return CAQR_ERR_ALLOC;
   p->device = device;
   DeviceGuard g(device);
+  if (!init_scratch(device)) {  // this device's copy of the no-allocation scratch array
+    delete p;
+    return CAQR_ERR_DEVICE;
+  }
   if (hipMalloc(&p->status_dev, 2 * sizeof(int64_t)) != hipSuccess) {
     delete p;
     return CAQR_ERR_ALLOC;
@@ -962,6 +1020,36 @@ caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, doub
   return caqr::ls_solve_ws(h, m, n, nrhs, A, lda, B, ldb, nullptr, info);
 }
 
+caqr_status_t ls_solve_noalloc(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
+                               int64_t ldb, caqr_ls_info_t *info) {
+  if (m < 0 || n < 0 || nrhs < 0 || lda < std::max<int64_t>(1, m) || ldb < std::max<int64_t>(1, m))
+    return CAQR_ERR_INVALID_VALUE;
+  if ((n > 0 && !A) || (nrhs > 0 && !B)) return CAQR_ERR_INVALID_VALUE;
+  if (m < n) return CAQR_ERR_NOT_SUPPORTED;
+  if (n > INT32_MAX || m / std::max<int64_t>(n, 1) > ((int64_t)1 << 40)) return CAQR_ERR_NOT_SUPPORTED;
+  // scratch layout: factors' workspace | ticket counters | two status words
+  const size_t ws = align256(caqr::ls_workspace_bytes(m, n));
+  const size_t counters = (size_t)ceil_div(std::max<int64_t>(m, 1), 256) * kTreeTiles;
+  const size_t tk = align256(counters * sizeof(unsigned));
+  if (ws + tk + 2 * sizeof(int64_t) > kScratchBytes) return CAQR_ERR_NOT_SUPPORTED;
+  if (!h) return CAQR_ERR_INVALID_VALUE;
+  if (info) {
+    info->status = CAQR_SUCCESS;
+    info->index = 0;
+  }
+  if (n == 0 || nrhs == 0) return CAQR_SUCCESS;
+  char *base = static_cast<char *>(scratch_ptr(h->device));  // resolved by caqr_create
+  if (!base) return CAQR_ERR_DEVICE;
+  DeviceGuard g(h->device);
+  unsigned *tickets = reinterpret_cast<unsigned *>(base + ws);
+  // counters start at zero (a fill kernel, not a memset node)
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(std::min<size_t>((counters + 255) / 256, 1024)), dim3(256), 0, h->stream,
+                     tickets, counters);
+  if (hipGetLastError() != hipSuccess) return CAQR_ERR_DEVICE;
+  return caqr::ls_solve_ws(h, m, n, nrhs, A, lda, B, ldb, base, info, tickets,
+                           reinterpret_cast<int64_t *>(base + ws + tk));
+}
+
 }  // extern "C"
 
 namespace caqr {
@@ -982,24 +1070,26 @@ caqr_status_t reserve_tickets(caqr_handle_t h, size_t counters) {
 // Arguments already validated.  With ws (ls_workspace_bytes(m, n) bytes), no
 // device memory is allocated or freed.
 caqr_status_t ls_solve_ws(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
-                          int64_t ldb, void *ws, caqr_ls_info_t *info) {
+                          int64_t ldb, void *ws, caqr_ls_info_t *info, unsigned *tickets, int64_t *status) {
   if (info) {
     info->status = CAQR_SUCCESS;
     info->index = 0;
   }
   if (n == 0 || nrhs == 0) return CAQR_SUCCESS;
   DeviceGuard g(h->device);
+  int64_t *status_dev = status ? status : h->status_dev;
   caqr_factors_t F = nullptr;
-  caqr_status_t st = (n <= kNbMax) ? factor_impl(h, m, n, std::max<int64_t>(n, 1), A, lda, nullptr, &F, true, ws)
-                                   : factor_impl(h, m, n, kNbMax, A, lda, nullptr, &F, false, ws);
+  caqr_status_t st =
+      (n <= kNbMax) ? factor_impl(h, m, n, std::max<int64_t>(n, 1), A, lda, nullptr, &F, true, ws, tickets)
+                    : factor_impl(h, m, n, kNbMax, A, lda, nullptr, &F, false, ws, tickets);
   if (st) return st;
   st = apply_q(h, F, CAQR_OP_T, nrhs, B, ldb);
   if (!st && forced_fault(h)) st = CAQR_ERR_DEVICE;
   if (!st && launch_trsm_upper(A, lda, n, B, ldb, nrhs, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
-  if (!st && launch_check_solution(A, lda, n, B, ldb, nrhs, h->status_dev, h->stream) != hipSuccess)
+  if (!st && launch_check_solution(A, lda, n, B, ldb, nrhs, status_dev, h->stream) != hipSuccess)
     st = CAQR_ERR_DEVICE;
   int64_t stat[2] = {0, 0};
-  if (!st && hipMemcpyAsync(stat, h->status_dev, sizeof(stat), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+  if (!st && hipMemcpyAsync(stat, status_dev, sizeof(stat), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
     st = CAQR_ERR_DEVICE;
   if (!st && hipStreamSynchronize(h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
   caqr_factors_destroy(F);

@@ -14,10 +14,15 @@ size_t ls_workspace_bytes(int64_t m, int64_t n);
 
 // Least-squares solve with validated arguments on the handle's stream.  With
 // ws (ls_workspace_bytes bytes of device memory, 256-byte aligned) the solve
-// allocates and frees no device memory; without, it allocates its own.
+// allocates and frees no device memory for its factors; without, it
+// allocates its own.  With tickets (zeroed counters, as many as the
+// factorization's trees need) the panel loop uses them instead of the
+// handle's and runs on the handle's stream alone; with status (two words of
+// device memory) the solution check writes there instead of the handle's.
 // Returns after the solve has finished (it reads back the status words).
 caqr_status_t ls_solve_ws(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *B,
-                          int64_t ldb, void *ws, caqr_ls_info_t *info);
+                          int64_t ldb, void *ws, caqr_ls_info_t *info, unsigned *tickets = nullptr,
+                          int64_t *status = nullptr);
 
 // Pre-size the handle's ticket counters (device-tree synchronization).
 caqr_status_t reserve_tickets(caqr_handle_t h, size_t counters);
