@@ -126,7 +126,7 @@ def batched_line(dtype_name: str):
     flops = float(sum(2.0 * int(m) * int(n) ** 2 - 2.0 * int(n) ** 3 / 3 for m, n in zip(ms, ns)))
     plans = {}
     for m, n in zip(ms, ns):
-        k = "h%d/lpw%d" % caqr.batch_plan_for(int(m), int(n), dtype=dtype)
+        k = "h%d/lpw%d/k%d" % caqr.batch_plan_for(int(m), int(n), dtype=dtype)
         plans[k] = plans.get(k, 0) + 1
     del P, W
     torch.cuda.empty_cache()
@@ -354,12 +354,13 @@ def tsqr_line(key):
     B = torch.empty_like(B0.t()).t()
     times = []
     reps = 20 if m2 > 4096 else 50
+    arity = 2 if key == "tsqr_4096x32" else 0  # 4096 x 32: its binary tree over 16 leaves
     for it in range(5 + reps):
         B.copy_(B0)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        G = caqr.tsqr(B)
+        G = caqr.tsqr(B, arity=arity)
         e1.record()
         torch.cuda.synchronize()
         if it >= 5:

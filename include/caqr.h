@@ -8,9 +8,10 @@
  * are stored in the lower part of A along a reduction tree (paper, Section 3.1
  * "Multilevel QR factorization", and Algorithm 1, ML-CAQR(A, m, n, r, P)).
  *
- *   tsqr_factor : one panel (n <= 64): a binary reduction tree of stacked-R
- *                 eliminations over row blocks (the panel step of Algorithm 1
- *                 and items 1(a)-1(b) of its description in Section 3.1).
+ *   tsqr_factor : one panel (n <= 64): a reduction tree (arity 2 or 4) of
+ *                 stacked-R eliminations over row blocks (the panel step of
+ *                 Algorithm 1 and items 1(a)-1(b) of its description in
+ *                 Section 3.1).
  *   caqr_factor : the panel loop of Algorithm 1: factor panel kk with the tree,
  *                 then update the trailing matrix with the leaf reflectors
  *                 (the MLUPFACT step) and the tree-node reflectors (the
@@ -71,7 +72,8 @@ typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
  *   leaf_rows      rows per leaf block: 64, 128 or 256 (default 256).
  *   leaves_per_wg  leaves one workgroup factors and combines in its own
  *                  registers/LDS before the device-wide tree: 1, 2 or 4
- *                  (default 1).  A single panel with 128 or more
+ *                  (default 1), a power of the arity (2 needs arity 2, and
+ *                  selects it when arity is 0).  A single panel with 128 or more
  *                  workgroups finishes the device-wide tree with one
  *                  launch per level instead of workgroups signalling each
  *                  other.
@@ -86,15 +88,25 @@ typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
  *                  every other call are unchanged.  tsqr_factor and
  *                  caqr_factor only: the batched calls return
  *                  CAQR_ERR_NOT_SUPPORTED for a nonzero value.
- * The tree is always the binary tree over leaves that pairs leaf i with leaf
- * i + 2^(k-1) at level k (i a multiple of 2^k), the lower index on top;
+ *   arity          members of every tree node: 2 (binary) or 4 (default 4;
+ *                  2 when leaves_per_wg is 2).  Level s = arity^j groups
+ *                  the row blocks (after the levels below) g, g + s, ...,
+ *                  g + (arity - 1) s, g a multiple of arity * s, the lowest
+ *                  index on top (for arity 2 the pairing of leaf i with leaf
+ *                  i + 2^(k-1) at level k); a node with fewer members at the
+ *                  end of a level eliminates those present.  A tree of arity
+ *                  4 has about half the levels of the binary tree, so half
+ *                  the sequential eliminations on the panel's critical
+ *                  path.  Inner blocks need arity 2 (CAQR_ERR_NOT_SUPPORTED
+ *                  otherwise).
  * leaves_per_wg only decides which levels run inside a workgroup, so R, Y, V
- * and tau are identical for every leaves_per_wg. */
+ * and tau are identical for every leaves_per_wg of one arity; different
+ * arities give the same R up to rounding (different Y, V and tau). */
 typedef struct {
   int32_t leaf_rows;
   int32_t leaves_per_wg;
   int32_t inner_block;
-  int32_t reserved; /* 0 */
+  int32_t arity; /* 0, 2 or 4 */
 } caqr_tree_opts_t;
 
 /* Summary of a factors object (host values). */
@@ -107,6 +119,7 @@ typedef struct {
   int32_t depth_panel0;   /* tree levels of the first panel */
   int32_t t_formed;       /* 1 when the T factors are materialized */
   int32_t inner_block;    /* inner block used (0: none) */
+  int32_t arity;          /* tree arity used (2 or 4) */
 } caqr_factors_info_t;
 
 /* Least-squares options and report. */
@@ -274,10 +287,11 @@ caqr_status_t caqr_trace_read(caqr_handle_t h, caqr_trace_entry_t *out, int64_t 
 /* Each problem i is the panel factorization of Section 3.1 (Algorithm 1,    */
 /* items 1(a)-1(b)) on its own: an m_i-by-n_i matrix (m_i >= n_i, n_i <= 64)  */
 /* is split into leaves, each factored by Householder QR, and the leaf R      */
-/* factors are eliminated along the binary tree, exactly as tsqr_factor does.  */
-/* All problems run in one launch per (leaf height, ceil(n_i/16)) group; the  */
-/* results of problem i are bitwise those of tsqr_factor on it with the same  */
-/* plan (leaf_rows, leaves_per_wg).  CAQR_F32 runs the same steps in single   */
+/* factors are eliminated along the tree of its plan's arity, exactly as      */
+/* tsqr_factor does.  All problems run in one launch per (leaf height,        */
+/* ceil(n_i/16), arity) group; the results of problem i are bitwise those of */
+/* tsqr_factor on it with the same plan (leaf_rows, leaves_per_wg, arity).    */
+/* CAQR_F32 runs the same steps in single                                     */
 /* precision (float storage and arithmetic throughout); its results do not    */
 /* depend on the other problems of the batch either.                          */
 /* ------------------------------------------------------------------------ */
@@ -306,7 +320,7 @@ caqr_status_t tsqr_factor_batched(caqr_handle_t h, int64_t batch, const int64_t 
 
 caqr_status_t caqr_batch_destroy(caqr_batch_t F);
 
-/* The plan used for problem i (leaf_rows, leaves_per_wg). */
+/* The plan used for problem i (leaf_rows, leaves_per_wg, arity). */
 caqr_status_t caqr_batch_get_plan(caqr_batch_t F, int64_t i, caqr_tree_opts_t *plan);
 
 /* Signs D of problem i (n_i doubles, host memory, also for CAQR_F32 batches);
@@ -314,7 +328,8 @@ caqr_status_t caqr_batch_get_plan(caqr_batch_t F, int64_t i, caqr_tree_opts_t *p
 caqr_status_t caqr_batch_get_signs(caqr_batch_t F, int64_t i, double *d);
 
 /* Autotuner: for n in {8, 16, 32, 64} and m in each power-of-two bucket from
-   256 to 65536, times every plan (leaf_rows 64/128/256 x leaves_per_wg 1/2/4)
+   256 to 65536, times every plan (leaf_rows 64/128/256 x (arity,
+   leaves_per_wg) in (2, 1), (2, 2), (2, 4), (4, 1), (4, 4))
    on a batch of synthetic problems of element type dt filling the device, and
    keeps the fastest in the handle, one table per dt (launch time only, by HIP
    events).  Later batched calls of that dt with opts == NULL use it: a

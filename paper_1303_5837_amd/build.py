@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcaqr.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["abi.hip", "panel.hip", "update.hip", "tfactor.hip", "ls.hip", "serve.hip", "lsb.hip"]
+SOURCES = ["abi.hip", "panel.hip", "panel_a4.hip", "panel_ib.hip", "panel_batched_f64.hip", "panel_batched_f32.hip",
+           "update.hip", "tfactor.hip", "ls.hip", "serve.hip", "lsb.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

@@ -41,14 +41,14 @@ class CaqrError(RuntimeError):
 
 class TreeOpts(ctypes.Structure):
     _fields_ = [("leaf_rows", ctypes.c_int32), ("leaves_per_wg", ctypes.c_int32),
-                ("inner_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("inner_block", ctypes.c_int32), ("arity", ctypes.c_int32)]
 
 
 class FactorsInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nb", ctypes.c_int64), ("panels", ctypes.c_int64),
                 ("leaf_rows", ctypes.c_int32), ("leaves_per_wg", ctypes.c_int32),
                 ("leaves_panel0", ctypes.c_int64), ("depth_panel0", ctypes.c_int32), ("t_formed", ctypes.c_int32),
-                ("inner_block", ctypes.c_int32)]
+                ("inner_block", ctypes.c_int32), ("arity", ctypes.c_int32)]
 
 
 class TraceEntry(ctypes.Structure):
@@ -248,10 +248,10 @@ def _ld(t: torch.Tensor, dtypes=(torch.float64,)) -> int:
     return max(1, t.stride(1) if n > 1 else m)
 
 
-def _opts(leaf_rows=0, leaves_per_wg=0, inner_block=0):
-    if not leaf_rows and not leaves_per_wg and not inner_block:
+def _opts(leaf_rows=0, leaves_per_wg=0, inner_block=0, arity=0):
+    if not leaf_rows and not leaves_per_wg and not inner_block and not arity:
         return None
-    return ctypes.byref(TreeOpts(leaf_rows, leaves_per_wg, inner_block, 0))
+    return ctypes.byref(TreeOpts(leaf_rows, leaves_per_wg, inner_block, arity))
 
 
 class Factors:
@@ -305,24 +305,24 @@ class Factors:
 
 
 def tsqr(A: torch.Tensor, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0,
-         inner_block: int = 0) -> Factors:
+         inner_block: int = 0, arity: int = 0) -> Factors:
     """In place TSQR of a column-major CUDA tensor; returns the factors (R = F.R)."""
     h = handle(device)
     m, n = A.shape
     f = ctypes.c_void_p()
     _check(_lib().tsqr_factor(h.ptr, m, n, ctypes.c_void_p(A.data_ptr()), _ld(A),
-                              _opts(leaf_rows, leaves_per_wg, inner_block), ctypes.byref(f)), "tsqr_factor")
+                              _opts(leaf_rows, leaves_per_wg, inner_block, arity), ctypes.byref(f)), "tsqr_factor")
     return Factors(h, f, A)
 
 
 def caqr(A: torch.Tensor, nb: int = 64, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0,
-         inner_block: int = 0) -> Factors:
+         inner_block: int = 0, arity: int = 0) -> Factors:
     """In place CAQR (panel width nb) of a column-major CUDA tensor."""
     h = handle(device)
     m, n = A.shape
     f = ctypes.c_void_p()
     _check(_lib().caqr_factor(h.ptr, m, n, nb, ctypes.c_void_p(A.data_ptr()), _ld(A),
-                              _opts(leaf_rows, leaves_per_wg, inner_block), ctypes.byref(f)), "caqr_factor")
+                              _opts(leaf_rows, leaves_per_wg, inner_block, arity), ctypes.byref(f)), "caqr_factor")
     return Factors(h, f, A)
 
 
@@ -360,9 +360,10 @@ class Batch:
         self.h, self._b, self.As = h, ptr, list(As)
 
     def plan(self, i: int):
+        """(leaf_rows, leaves_per_wg, arity) of problem i."""
         o = TreeOpts()
         _check(_lib().caqr_batch_get_plan(self._b, i, ctypes.byref(o)), "caqr_batch_get_plan")
-        return int(o.leaf_rows), int(o.leaves_per_wg)
+        return int(o.leaf_rows), int(o.leaves_per_wg), int(o.arity)
 
     def signs(self, i: int):
         import numpy as np
@@ -397,7 +398,7 @@ def _dtype_code(dtype) -> int:
     return _DT[dtype]
 
 
-def tsqr_batched(As, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0) -> Batch:
+def tsqr_batched(As, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0, arity: int = 0) -> Batch:
     """In place TSQR of every column-major CUDA tensor in ``As`` (all float64 or
     all float32; one plan for all when leaf_rows/leaves_per_wg are given, else
     the tuned or default plans of that type)."""
@@ -410,12 +411,12 @@ def tsqr_batched(As, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0
     ld = (ctypes.c_int64 * max(1, k))(*[_ld(a, (dtype,)) for a in As])
     ptrs = (ctypes.c_void_p * max(1, k))(*[a.data_ptr() for a in As])
     b = ctypes.c_void_p()
-    _check(_lib().tsqr_factor_batched(h.ptr, k, m, n, ptrs, ld, dt, _opts(leaf_rows, leaves_per_wg),
+    _check(_lib().tsqr_factor_batched(h.ptr, k, m, n, ptrs, ld, dt, _opts(leaf_rows, leaves_per_wg, 0, arity),
                                       ctypes.byref(b)), "tsqr_factor_batched")
     return Batch(h, b, As)
 
 
-def ls_solve_batched(As, Bs, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0):
+def ls_solve_batched(As, Bs, leaf_rows: int = 0, leaves_per_wg: int = 0, device: int = 0, arity: int = 0):
     """Batched least squares in place (n_i <= 64, float64, column-major CUDA
     tensors): returns ([X_i = B_i[:n_i]], [(status, index)]); raises only on
     argument or device errors."""
@@ -430,7 +431,7 @@ def ls_solve_batched(As, Bs, leaf_rows: int = 0, leaves_per_wg: int = 0, device:
     pa = (ctypes.c_void_p * max(1, k))(*[a.data_ptr() for a in As])
     pb = (ctypes.c_void_p * max(1, k))(*[b.data_ptr() for b in Bs])
     info = (LsInfo * max(1, k))()
-    code = _lib().ls_solve_batched(h.ptr, k, m, n, r, pa, la, pb, lb, _opts(leaf_rows, leaves_per_wg), info)
+    code = _lib().ls_solve_batched(h.ptr, k, m, n, r, pa, la, pb, lb, _opts(leaf_rows, leaves_per_wg, 0, arity), info)
     if code not in (0, 5, 6):
         _check(code, "ls_solve_batched")
     return [b[: a.shape[1]] for a, b in zip(As, Bs)], [(int(info[i].status), int(info[i].index)) for i in range(k)]
@@ -443,11 +444,11 @@ def tune_batched(device: int = 0, dtype=torch.float64):
 
 
 def batch_plan_for(m: int, n: int, device: int = 0, dtype=torch.float64):
-    """(leaf_rows, leaves_per_wg) a batched call without a plan uses for an m-by-n problem."""
+    """(leaf_rows, leaves_per_wg, arity) a batched call without a plan uses for an m-by-n problem."""
     h = handle(device)
     o = TreeOpts()
     _check(_lib().caqr_batch_plan_for(h.ptr, m, n, _dtype_code(dtype), ctypes.byref(o)), "caqr_batch_plan_for")
-    return int(o.leaf_rows), int(o.leaves_per_wg)
+    return int(o.leaf_rows), int(o.leaves_per_wg), int(o.arity)
 
 
 class Server:

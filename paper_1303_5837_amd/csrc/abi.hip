@@ -24,6 +24,8 @@ using namespace caqr;
 namespace {
 
 constexpr int kNbMax = 64;
+// Tree arity of a factorization whose options leave it open.
+constexpr int kDefaultArity = 4;
 
 struct DeviceGuard {
   int prev = -1;
@@ -128,16 +130,16 @@ struct caqr_batch_s {
   std::vector<caqr::PanelParams32> probs32;  // probs32 before the upload
   std::vector<int2> items;              // (problem within its group, first leaf) per workgroup
   struct Group {
-    int leaf_rows, nq;
+    int leaf_rows, nq, arity;
     int64_t prob0, nprob, item0, nitem, rows, leaves;
   };
   std::vector<Group> groups;
   // device tree levels: round k holds every problem's k-th level above its
-  // workgroups' leaves, one launch per (round, nq): nodes (problem, left
-  // slot, right slot, leaf rows | root << 16)
+  // workgroups' leaves, one launch per (round, arity, nq): nodes (problem,
+  // survivor slot, stride, leaf rows | root << 12 | members << 16)
   std::vector<int4> nodes;
   struct Level {
-    int nq;
+    int nq, arity;
     int64_t node0, nnode;
   };
   std::vector<Level> levels;
@@ -152,6 +154,7 @@ struct caqr_factors_s {
   int64_t m = 0, n = 0, nb = 0, lda = 0;
   double *A = nullptr;
   int leaf_rows = 256, lpw = 1;
+  int arity = kDefaultArity;  // of every panel's tree
   int inner_block = 0;      // 16 or 32: leaves and eliminations factored in inner blocks
   std::vector<PanelRec> panels;
   double *small = nullptr;  // tau and d of all panels
@@ -277,7 +280,7 @@ size_t factor_ws_bytes(int64_t m, int64_t n, int64_t nb, int leaf_rows, size_t *
 // buffers are carved from it (factor_ws_bytes bytes, 256-byte aligned) and
 // stay the lender's.
 caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda, int leaf_rows,
-                           int lpw, bool eager_t, void *ws, caqr_factors_t *out) {
+                           int lpw, int arity, bool eager_t, void *ws, caqr_factors_t *out) {
   caqr_factors_s *F = new (std::nothrow) caqr_factors_s;
   if (!F) return CAQR_ERR_ALLOC;
   F->device = h->device;
@@ -288,6 +291,7 @@ caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, do
   F->A = A;
   F->leaf_rows = leaf_rows;
   F->lpw = lpw;
+  F->arity = arity;
   F->limit = h->ws_limit;
   size_t small_doubles = 0, t_doubles = 0;
   for (int64_t c0 = 0; c0 < n; c0 += nb) {
@@ -363,6 +367,7 @@ PanelParams panel_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p) {
   pp.b = p.b;
   pp.L = p.L;
   pp.lpw = F->lpw;
+  pp.arity = F->arity;
   pp.tau_leaf = p.tau_leaf;
   pp.tau_node = p.tau_node;
   pp.d = p.d;
@@ -385,7 +390,8 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
   u.T_node = p.T_node;
   u.d = p.d;
   u.tiles = ceil_div(k, kUpdTile);
-  u.level = 0;
+  u.arity = F->arity;
+  u.stride = 0;
   u.tickets = nullptr;
   return u;
 }
@@ -412,6 +418,7 @@ caqr_status_t launch_panel_t(caqr_handle_t h, caqr_factors_t F, int idx, hipStre
   f.b = p.b;
   f.L = p.L;
   f.h = F->leaf_rows;
+  f.arity = F->arity;
   f.tau_leaf = p.tau_leaf;
   f.tau_node = p.tau_node;
   f.T_leaf = p.T_leaf;
@@ -440,8 +447,8 @@ caqr_status_t launch_panel(caqr_handle_t h, caqr_factors_t F, int idx, bool form
     TraceScope ts(h, CAQR_TRACE_PANEL, idx, p.m, p.b, p.b, p.L, st);
     if (levels) pp.tickets = nullptr;
     if (launch_tsqr_panel(pp, F->leaf_rows, st, !levels, F->inner_block) != hipSuccess) return CAQR_ERR_DEVICE;
-    for (int half = F->lpw; levels && half < p.L; half *= 2)
-      if (launch_tsqr_level(pp, half, F->leaf_rows, st, F->inner_block) != hipSuccess) return CAQR_ERR_DEVICE;
+    for (int s = F->lpw; levels && s < p.L; s *= F->arity)
+      if (launch_tsqr_level(pp, s, F->leaf_rows, st, F->inner_block) != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return form_t ? launch_panel_t(h, F, idx, st) : CAQR_SUCCESS;
 }
@@ -526,6 +533,7 @@ caqr_status_t ensure_t(caqr_handle_t h, caqr_factors_t F) {
 // Size and pointer checks come first, then the handle, so that every argument
 // error is reported the same way with or without a device.
 caqr_status_t check_opts(const caqr_tree_opts_t *o);
+bool inner_block_unsupported(const caqr_tree_opts_t *o);
 
 caqr_status_t check_common(caqr_handle_t h, int64_t m, int64_t n, const double *A, int64_t lda, caqr_factors_t *F,
                            const caqr_tree_opts_t *opts) {
@@ -533,7 +541,7 @@ caqr_status_t check_common(caqr_handle_t h, int64_t m, int64_t n, const double *
   if (check_opts(opts)) return CAQR_ERR_INVALID_VALUE;
   if (m < 0 || n < 0 || lda < std::max<int64_t>(1, m)) return CAQR_ERR_INVALID_VALUE;
   if (n > 0 && !A) return CAQR_ERR_INVALID_VALUE;
-  if (m < n) return CAQR_ERR_NOT_SUPPORTED;
+  if (m < n || inner_block_unsupported(opts)) return CAQR_ERR_NOT_SUPPORTED;
   if (n > INT32_MAX || m / std::max<int64_t>(n, 1) > ((int64_t)1 << 40)) return CAQR_ERR_NOT_SUPPORTED;
   if (!h) return CAQR_ERR_INVALID_VALUE;
   return CAQR_SUCCESS;
@@ -544,10 +552,26 @@ caqr_status_t check_opts(const caqr_tree_opts_t *o) {
   if (o->leaf_rows && !valid_leaf_rows(o->leaf_rows)) return CAQR_ERR_INVALID_VALUE;
   if (o->leaves_per_wg && o->leaves_per_wg != 1 && o->leaves_per_wg != 2 && o->leaves_per_wg != 4)
     return CAQR_ERR_INVALID_VALUE;
+  if (o->arity && o->arity != 2 && o->arity != 4) return CAQR_ERR_INVALID_VALUE;
+  // leaves per workgroup: a power of the arity (whole subtrees per workgroup)
+  if (o->arity == 4 && o->leaves_per_wg == 2) return CAQR_ERR_INVALID_VALUE;
   if (o->inner_block && o->inner_block != 16 && o->inner_block != 32 && o->inner_block != 64)
     return CAQR_ERR_INVALID_VALUE;
-  if (o->reserved) return CAQR_ERR_INVALID_VALUE;
   return CAQR_SUCCESS;
+}
+
+// The arity asked for; when it is left open, the binary tree for options
+// that need one (two leaves per workgroup, not a power of four; inner
+// blocks), else the default arity.
+int resolve_arity(const caqr_tree_opts_t *o) {
+  if (o && o->arity) return o->arity;
+  if (o && (o->leaves_per_wg == 2 || (o->inner_block && o->inner_block < kNbMax))) return 2;
+  return kDefaultArity;
+}
+
+// Inner blocks are built for binary trees only.
+bool inner_block_unsupported(const caqr_tree_opts_t *o) {
+  return o && o->inner_block && o->inner_block < kNbMax && resolve_arity(o) != 2;
 }
 
 caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
@@ -558,7 +582,7 @@ caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, dou
   const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : 1;
   DeviceGuard g(h->device);
   caqr_factors_t f = nullptr;
-  caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, !tsqr, ws, &f);
+  caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, resolve_arity(opts), !tsqr, ws, &f);
   if (st) return st;
   f->inner_block = (opts && opts->inner_block < kNbMax) ? opts->inner_block : 0;
   if (tickets) {  // lent counters: no allocation and no second stream
@@ -598,13 +622,15 @@ int m_bucket(int64_t m) {
 }
 
 // Plan of one problem when the caller gives none: the tuned table, else leaf
-// height by size and as many leaves per workgroup as keep four or more of them.
+// height by size, a binary tree and as many leaves per workgroup as keep four
+// or more of them.
 caqr_tree_opts_t default_plan(caqr_handle_t h, int64_t m, int64_t n, caqr_dtype_t dt) {
   if (h->tuned[dt]) return h->tuned_plan[dt][n_bucket(n)][m_bucket(m)];
   caqr_tree_opts_t o{};
   o.leaf_rows = m >= 1024 ? 256 : (m >= 256 ? 128 : 64);
   const int64_t L = (m + o.leaf_rows - 1) / o.leaf_rows;
   o.leaves_per_wg = L >= 16 ? 4 : (L >= 4 ? 2 : 1);
+  o.arity = 2;
   return o;
 }
 
@@ -646,6 +672,7 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
     caqr_tree_opts_t o = opts ? *opts : default_plan(h, m[i], n[i], dt);
     if (!o.leaf_rows) o.leaf_rows = 256;
     if (!o.leaves_per_wg) o.leaves_per_wg = 4;
+    o.arity = resolve_arity(&o);
     B->plan[i] = o;
     if (n[i] == 0) continue;
     L[i] = (m[i] + o.leaf_rows - 1) / o.leaf_rows;
@@ -654,14 +681,19 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
     B->d_off[i] = small_elems;
     small_elems += kNbMax;
   }
-  // groups in a fixed order: leaf rows 64/128/256, then nq 1..4
+  // groups in a fixed order: arity 2/4, leaf rows 64/128/256, then nq 1..4
   static const int kLeaf[3] = {64, 128, 256};
-  std::vector<std::array<std::vector<int4>, 4>> round_nodes(32);
+  static const int kArity[2] = {2, 4};
+  // device-level nodes by (round, arity, nq)
+  std::vector<std::array<std::array<std::vector<int4>, 4>, 2>> round_nodes(32);
+  for (int ai = 0; ai < 2; ++ai)
   for (int hi = 0; hi < 3; ++hi)
     for (int nq = 1; nq <= 4; ++nq) {
-      caqr_batch_s::Group g{kLeaf[hi], nq, (int64_t)B->probs.size(), 0, (int64_t)B->items.size(), 0, 0, 0};
+      const int K = kArity[ai];
+      caqr_batch_s::Group g{kLeaf[hi], nq, K, (int64_t)B->probs.size(), 0, (int64_t)B->items.size(), 0, 0, 0};
       for (int64_t i = 0; i < batch; ++i) {
-        if (n[i] == 0 || B->plan[i].leaf_rows != kLeaf[hi] || (n[i] + 15) / 16 != nq) continue;
+        if (n[i] == 0 || B->plan[i].leaf_rows != kLeaf[hi] || (n[i] + 15) / 16 != nq || B->plan[i].arity != K)
+          continue;
         caqr::PanelParams p{};  // pointers hold offsets until the buffers exist
         p.A = static_cast<double *>(A[i]);
         p.lda = lda[i];
@@ -669,19 +701,23 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
         p.b = (int)n[i];
         p.L = (int)L[i];
         p.lpw = B->plan[i].leaves_per_wg;
+        p.arity = K;
         p.tau_leaf = reinterpret_cast<double *>(tau_off[i]);  // offsets; rebased after allocation
         p.tau_node = reinterpret_cast<double *>(tau_off[i] + L[i] * kNbMax);
         p.d = reinterpret_cast<double *>(B->d_off[i]);
         p.tickets = nullptr;  // the device levels are separate launches
-        // device levels: pairs (left, left + half) for half = lpw, 2 lpw, ...
+        // device levels: groups of survivor g at stride s = lpw, K lpw, ...
+        // (members g + t s < L, two or more of them)
         {
           const int64_t gidx = (int64_t)B->probs.size();
           int k = 0;
-          for (int64_t half = p.lpw; half < L[i]; half <<= 1, ++k) {
-            const bool top = 2 * half >= L[i];
-            for (int64_t left = 0; left + half < L[i]; left += 2 * half)
-              round_nodes[(size_t)k][nq - 1].push_back(
-                  int4{(int)gidx, (int)left, (int)(left + half), kLeaf[hi] | ((top ? 1 : 0) << 16)});
+          for (int64_t st = p.lpw; st < L[i]; st *= K, ++k) {
+            const bool top = K * st >= L[i];
+            for (int64_t g0 = 0; g0 + st < L[i]; g0 += K * st) {
+              const int cnt = (int)std::min<int64_t>(K, (L[i] - g0 + st - 1) / st);
+              round_nodes[(size_t)k][ai][nq - 1].push_back(
+                  int4{(int)gidx, (int)g0, (int)st, kLeaf[hi] | ((top ? 1 : 0) << 12) | (cnt << 16)});
+            }
           }
         }
         const int local = (int)(B->probs.size() - g.prob0);
@@ -696,11 +732,13 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
       if (g.nprob) B->groups.push_back(g);
     }
   for (auto &rd : round_nodes)
-    for (int q = 0; q < 4; ++q) {
-      if (rd[q].empty()) continue;
-      B->levels.push_back(caqr_batch_s::Level{q + 1, (int64_t)B->nodes.size(), (int64_t)rd[q].size()});
-      B->nodes.insert(B->nodes.end(), rd[q].begin(), rd[q].end());
-    }
+    for (int ai = 0; ai < 2; ++ai)
+      for (int q = 0; q < 4; ++q) {
+        if (rd[ai][q].empty()) continue;
+        B->levels.push_back(
+            caqr_batch_s::Level{q + 1, kArity[ai], (int64_t)B->nodes.size(), (int64_t)rd[ai][q].size()});
+        B->nodes.insert(B->nodes.end(), rd[ai][q].begin(), rd[ai][q].end());
+      }
   const size_t es = elem_size(dt);
   const size_t table_bytes = B->probs.size() * (dt == CAQR_F32 ? sizeof(caqr::PanelParams32) : sizeof(caqr::PanelParams));
   const size_t bytes =
@@ -729,6 +767,7 @@ caqr_status_t batch_prepare(caqr_handle_t h, int64_t batch, const int64_t *m, co
       q.b = p.b;
       q.L = p.L;
       q.lpw = p.lpw;
+      q.arity = p.arity;
       q.tau_leaf = small + reinterpret_cast<intptr_t>(p.tau_leaf);
       q.tau_node = small + reinterpret_cast<intptr_t>(p.tau_node);
       q.d = small + reinterpret_cast<intptr_t>(p.d);
@@ -771,9 +810,9 @@ caqr_status_t batch_launch(caqr_handle_t h, caqr_batch_t B) {
     const hipError_t e =
         B->dt == CAQR_F32
             ? launch_tsqr_panel_batched(static_cast<const caqr::PanelParams32 *>(B->probs_dev) + g.prob0,
-                                        B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, h->stream)
+                                        B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, g.arity, h->stream)
             : launch_tsqr_panel_batched(static_cast<const caqr::PanelParams *>(B->probs_dev) + g.prob0,
-                                        B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, h->stream);
+                                        B->items_dev + g.item0, (int)g.nitem, g.leaf_rows, g.nq, g.arity, h->stream);
     if (e != hipSuccess) return CAQR_ERR_DEVICE;
   }
   for (size_t li = 0; li < B->levels.size(); ++li) {
@@ -782,9 +821,9 @@ caqr_status_t batch_launch(caqr_handle_t h, caqr_batch_t B) {
     const hipError_t e =
         B->dt == CAQR_F32
             ? launch_tsqr_tree_level(static_cast<const caqr::PanelParams32 *>(B->probs_dev), B->nodes_dev + l.node0,
-                                     (int)l.nnode, l.nq, h->stream)
+                                     (int)l.nnode, l.nq, l.arity, h->stream)
             : launch_tsqr_tree_level(static_cast<const caqr::PanelParams *>(B->probs_dev), B->nodes_dev + l.node0,
-                                     (int)l.nnode, l.nq, h->stream);
+                                     (int)l.nnode, l.nq, l.arity, h->stream);
     if (e != hipSuccess) return CAQR_ERR_DEVICE;
   }
   return CAQR_SUCCESS;
@@ -990,11 +1029,12 @@ caqr_status_t caqr_factors_get_info(caqr_factors_t F, caqr_factors_info_t *info)
   if (!F->panels.empty()) {
     info->leaves_panel0 = F->panels[0].L;
     int depth = 0;
-    while ((1 << depth) < F->panels[0].L) ++depth;
+    for (int64_t span = 1; span < F->panels[0].L; span *= F->arity) ++depth;
     info->depth_panel0 = depth;
   }
   info->t_formed = F->t_formed ? 1 : 0;
   info->inner_block = F->inner_block;
+  info->arity = F->arity;
   return CAQR_SUCCESS;
 }
 
@@ -1177,8 +1217,8 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
   const size_t elems = (size_t)kRows * kNbMax;
   const size_t es = elem_size(dt);
   if (h->ws_limit && elems * es > h->ws_limit) return CAQR_ERR_ALLOC;
-  char *scratch = nullptr;
-  if (hipMalloc(&scratch, elems * es) != hipSuccess) return CAQR_ERR_ALLOC;
+  char *tune_buf = nullptr;  // the synthetic problems
+  if (hipMalloc(&tune_buf, elems * es) != hipSuccess) return CAQR_ERR_ALLOC;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   caqr_status_t st = CAQR_SUCCESS;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = CAQR_ERR_DEVICE;
@@ -1186,7 +1226,9 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
   h->trace = false;
   static const int kN[4] = {8, 16, 32, 64};
   static const int kLeaf[3] = {64, 128, 256};
-  static const int kLpw[3] = {1, 2, 4};
+  // (leaves per workgroup, arity): every power of the arity up to four
+  static const int kLpw[5] = {1, 2, 4, 1, 4};
+  static const int kAr[5] = {2, 2, 2, 4, 4};
   caqr_tree_opts_t table[4][9] = {};
   for (int nb = 0; nb < 4 && !st; ++nb)
     for (int mb = 0; mb < 9 && !st; ++mb) {
@@ -1195,23 +1237,24 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
       const int64_t K = std::max<int64_t>(1, kRows / mm);
       std::vector<int64_t> mv(K, mm), nv(K, nn), lv(K, mm);
       std::vector<void *> av(K);
-      for (int64_t i = 0; i < K; ++i) av[i] = scratch + (size_t)(i * mm * nn) * es;
+      for (int64_t i = 0; i < K; ++i) av[i] = tune_buf + (size_t)(i * mm * nn) * es;
       float best = 0.f;
       for (int hi = 0; hi < 3 && !st; ++hi)
-        for (int li = 0; li < 3 && !st; ++li) {
+        for (int li = 0; li < 5 && !st; ++li) {
           caqr_tree_opts_t o{};
           o.leaf_rows = kLeaf[hi];
           o.leaves_per_wg = kLpw[li];
+          o.arity = kAr[li];
           caqr_batch_t B = nullptr;
           if ((st = batch_prepare(h, K, mv.data(), nv.data(), av.data(), lv.data(), dt, &o, &B))) break;
           float ts[5];
           for (int rep = 0; rep < 5 && !st; ++rep) {
             if (dt == CAQR_F32)
               hipLaunchKernelGGL(fill_pattern_kernel<float>, dim3(1024), dim3(256), 0, h->stream,
-                                 reinterpret_cast<float *>(scratch), (size_t)(K * mm * nn));
+                                 reinterpret_cast<float *>(tune_buf), (size_t)(K * mm * nn));
             else
               hipLaunchKernelGGL(fill_pattern_kernel<double>, dim3(1024), dim3(256), 0, h->stream,
-                                 reinterpret_cast<double *>(scratch), (size_t)(K * mm * nn));
+                                 reinterpret_cast<double *>(tune_buf), (size_t)(K * mm * nn));
             if (hipEventRecord(e0, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
             if (!st) st = batch_launch(h, B);
             if (!st && hipEventRecord(e1, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
@@ -1231,7 +1274,7 @@ caqr_status_t caqr_tune_batched(caqr_handle_t h, caqr_dtype_t dt) {
   h->trace = trace;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  (void)hipFree(scratch);
+  (void)hipFree(tune_buf);
   if (st) return st;
   std::memcpy(h->tuned_plan[dt], table, sizeof(table));
   h->tuned[dt] = true;
@@ -1294,6 +1337,7 @@ caqr_status_t ls_solve_batched(caqr_handle_t h, int64_t batch, const int64_t *m,
     q.b = pp.b;
     q.L = pp.L;
     q.h = Bt->plan[s].leaf_rows;
+    q.arity = Bt->plan[s].arity;
     q.tau_leaf = pp.tau_leaf;
     q.tau_node = pp.tau_node;
     q.d = pp.d;
@@ -1305,10 +1349,9 @@ caqr_status_t ls_solve_batched(caqr_handle_t h, int64_t batch, const int64_t *m,
     for (int r = 0; r < q.nrhs; ++r) {
       for (int l = 0; l < q.L; ++l) leaf_items.push_back(int4{(int)s, l, r, 0});
       int k = 0;
-      for (int half = 1; half < q.L; half <<= 1, ++k) {
+      for (int st = 1; st < q.L; st *= q.arity, ++k) {  // groups of survivor g0, stride st
         if ((int)by_level.size() <= k) by_level.resize(k + 1);
-        for (int left = 0; left + half < q.L; left += 2 * half)
-          by_level[k].push_back(int4{(int)s, left, left + half, r});
+        for (int g0 = 0; g0 + st < q.L; g0 += q.arity * st) by_level[k].push_back(int4{(int)s, g0, st, r});
       }
       solve_items.push_back(int2{(int)s, r});
     }

@@ -21,9 +21,10 @@ struct PanelParamsT {
   int64_t m;
   int b;          // panel width, 1..64
   int L;          // number of leaves (row blocks of leaf_rows rows)
-  int lpw;        // leaves per workgroup (1, 2, 4)
+  int lpw;        // leaves per workgroup (1, 2, 4; a power of arity)
+  int arity;      // tree arity K: 2 or 4
   T *tau_leaf;    // [L][64]
-  T *tau_node;    // [L][64], node id = eliminated leaf (1..L-1)
+  T *tau_node;    // [L][64], node id = first eliminated member g + s (1..L-1)
   T *d;           // [64] signs of the root R
   unsigned *tickets;  // [L], zero on entry and on exit
 };
@@ -46,36 +47,40 @@ struct UpdateParams {
   const double *T_node;
   const double *d;    // signs
   int tiles;          // column tiles of kUpdTile
-  int level;          // node kernels: tree level processed (half = 1 << (level-1))
+  int arity;          // tree arity K: 2 or 4
+  int stride;         // node kernels: tree level processed, as its stride s = K^j
   unsigned *tickets;  // [kTreeTiles * L] zero on entry and exit, or null; with
                       // tickets, a Q^T of at most kTreeTiles tiles runs the
                       // whole tree in one launch
 };
 
-// Leaves and tree of one panel.  With device_tree (tickets required), the
-// workgroups climb the whole tree; without, each stops at its own subtree
-// and launch_tsqr_level finishes the tree, one launch per level.
-// inner_block (0, 16 or 32; no effect unless narrower than the panel): every
-// leaf and stacked elimination is factored in inner blocks of that many
-// columns, each block applied to the columns right of it at once.
+// Leaves and tree (arity p.arity) of one panel.  With device_tree (tickets
+// required), the workgroups climb the whole tree; without, each stops at its
+// own subtree and launch_tsqr_level finishes the tree, one launch per level.
+// inner_block (0, 16 or 32; no effect unless narrower than the panel; binary
+// trees only): every leaf and stacked elimination is factored in inner blocks
+// of that many columns, each block applied to the columns right of it at once.
 hipError_t launch_tsqr_panel(const PanelParams &p, int leaf_rows, hipStream_t s, bool device_tree = true,
                              int inner_block = 0);
-// Level `half` (pairs (left, left + half), left a multiple of 2 half) of one
-// panel's tree; the top level also normalizes the root.
-hipError_t launch_tsqr_level(const PanelParams &p, int half, int leaf_rows, hipStream_t s, int inner_block = 0);
+// Level s (groups of survivor g = K s i, members g + t s) of one panel's
+// tree; the top level also normalizes the root.
+hipError_t launch_tsqr_level(const PanelParams &p, int s, int leaf_rows, hipStream_t st, int inner_block = 0);
 
-// Independent panels of equal ceil(b/16) = nq and leaf height in one launch:
-// probs (device) holds one PanelParams per problem, items (device) one
-// (problem, first leaf) pair per workgroup; each workgroup stops at the tree
-// levels that join its leaves with another workgroup's.
+// Independent panels of equal ceil(b/16) = nq, leaf height and tree arity in
+// one launch: probs (device) holds one PanelParams per problem, items
+// (device) one (problem, first leaf) pair per workgroup; each workgroup stops
+// at the tree levels that join its leaves with another workgroup's.
 hipError_t launch_tsqr_panel_batched(const PanelParams *probs, const int2 *items, int nitems, int leaf_rows, int nq,
-                                     hipStream_t s);
+                                     int arity, hipStream_t s);
 hipError_t launch_tsqr_panel_batched(const PanelParams32 *probs, const int2 *items, int nitems, int leaf_rows, int nq,
-                                     hipStream_t s);
-// One device-level tree step of many panels of equal ceil(b/16) = nq: node
-// (problem, left slot, right slot, leaf rows | root << 16) per workgroup.
-hipError_t launch_tsqr_tree_level(const PanelParams *probs, const int4 *nodes, int nnodes, int nq, hipStream_t s);
-hipError_t launch_tsqr_tree_level(const PanelParams32 *probs, const int4 *nodes, int nnodes, int nq, hipStream_t s);
+                                     int arity, hipStream_t s);
+// One device-level tree step of many panels of equal ceil(b/16) = nq and
+// arity: node (problem, survivor slot g, stride s, leaf rows | root << 12 |
+// members << 16) per workgroup.
+hipError_t launch_tsqr_tree_level(const PanelParams *probs, const int4 *nodes, int nnodes, int nq, int arity,
+                                  hipStream_t s);
+hipError_t launch_tsqr_tree_level(const PanelParams32 *probs, const int4 *nodes, int nnodes, int nq, int arity,
+                                  hipStream_t s);
 
 // C <- Q^T C for one panel: leaf updates and the tree bottom-up, then rows
 // 0..b-1 scaled by D.  One workgroup per (leaf, tile), then one launch per
@@ -94,6 +99,7 @@ struct FormTParams {
   int64_t ldy;
   int64_t m;
   int b, L, h;
+  int arity;        // tree arity K: 2 or 4
   const double *tau_leaf, *tau_node;
   double *T_leaf, *T_node;
 };

@@ -77,36 +77,60 @@ __global__ void __launch_bounds__(64 * kLsbWaves) lsb_leaf_kernel(const LsbProb 
     if (ok[k]) bc[r0 + lane + 64 * k] = bv[k];
 }
 
-// Node reflectors of the elimination of slot items[w].z against slot
-// items[w].y of problem items[w].x, applied to right-hand side items[w].w:
-// lane i holds row i of both slots' top b rows.  Reflector j is
-// [e_j ; V(0:j, j)], V upper triangular over the eliminated slot.
+// Node reflectors of the group of survivor slot items[w].y at stride
+// items[w].z of problem items[w].x (members g + t s, t < cnt <= arity),
+// applied to right-hand side items[w].w: lane i holds row i of every member's
+// top b rows.  Reflector j is [e_j ; V_1(0:j, j) ; ... ; V_{cnt-1}(0:j, j)],
+// each V_t upper triangular over member t's slot; its dot product sums the
+// members' products in each lane first, then over the wave.
 __global__ void __launch_bounds__(64 * kLsbWaves) lsb_node_kernel(const LsbProb *probs, const int4 *items,
                                                                   int nitems) {
+  constexpr int KMAX = 4;  // largest arity
   const int wv = (int)blockIdx.x * kLsbWaves + (int)(threadIdx.x >> 6);
   if (wv >= nitems) return;
   const int lane = threadIdx.x & 63;
   const int4 it = items[wv];
   const LsbProb p = probs[__builtin_amdgcn_readfirstlane(it.x)];
-  const int left = __builtin_amdgcn_readfirstlane(it.y);
-  const int right = __builtin_amdgcn_readfirstlane(it.z);
+  const int g = __builtin_amdgcn_readfirstlane(it.y);
+  const int s = __builtin_amdgcn_readfirstlane(it.z);
   const int rhs = __builtin_amdgcn_readfirstlane(it.w);
-  const int64_t rt = (int64_t)left * p.h + lane, rc = (int64_t)right * p.h + lane;
-  const bool okt = lane < p.b && rt < p.m, okc = lane < p.b && rc < p.m;
+  const int cnt = min(p.arity, (p.L - g + s - 1) / s);
   double *bc = p.B + (int64_t)rhs * p.ldb;
-  double top = okt ? bc[rt] : 0.0, child = okc ? bc[rc] : 0.0;
-  double vv = (okc && lane == 0) ? p.A[rc] : 0.0;  // column 0 of V
+  const int64_t rt = (int64_t)g * p.h + lane;
+  const bool okt = lane < p.b && rt < p.m;
+  double top = okt ? bc[rt] : 0.0;
+  int64_t rc[KMAX - 1];
+  bool okc[KMAX - 1];
+  double child[KMAX - 1], vv[KMAX - 1];
+#pragma unroll
+  for (int t = 0; t < KMAX - 1; ++t) {
+    rc[t] = (int64_t)(g + (t + 1) * s) * p.h + lane;
+    okc[t] = t + 1 < cnt && lane < p.b && rc[t] < p.m;
+    child[t] = okc[t] ? bc[rc[t]] : 0.0;
+    vv[t] = (okc[t] && lane == 0) ? p.A[rc[t]] : 0.0;  // column 0 of V_t
+  }
   for (int j = 0; j < p.b; ++j) {
-    const double vn = (okc && j + 1 < p.b && lane <= j + 1) ? p.A[rc + (int64_t)(j + 1) * p.lda] : 0.0;
-    const double tau = p.tau_node[(int64_t)right * kMaxB + j];
-    const double w = readlane_f64(top, j) + wave_sum(vv * child);
+    double vn[KMAX - 1];
+#pragma unroll
+    for (int t = 0; t < KMAX - 1; ++t)
+      vn[t] = (okc[t] && j + 1 < p.b && lane <= j + 1) ? p.A[rc[t] + (int64_t)(j + 1) * p.lda] : 0.0;
+    const double tau = p.tau_node[(int64_t)(g + s) * kMaxB + j];
+    double prod = vv[0] * child[0];
+#pragma unroll
+    for (int t = 1; t < KMAX - 1; ++t) prod = fma(vv[t], child[t], prod);
+    const double w = readlane_f64(top, j) + wave_sum(prod);
     const double tw = tau * w;
     if (lane == j) top -= tw;
-    child = fma(-tw, vv, child);
-    vv = vn;
+#pragma unroll
+    for (int t = 0; t < KMAX - 1; ++t) {
+      child[t] = fma(-tw, vv[t], child[t]);
+      vv[t] = vn[t];
+    }
   }
   if (okt) bc[rt] = top;
-  if (okc) bc[rc] = child;
+#pragma unroll
+  for (int t = 0; t < KMAX - 1; ++t)
+    if (okc[t]) bc[rc[t]] = child[t];
 }
 
 // Rows 0..n-1 of right-hand side items[w].y of problem items[w].x: scaled by

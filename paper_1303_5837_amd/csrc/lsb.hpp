@@ -14,6 +14,7 @@ struct LsbProb {
   const double *A;
   int64_t lda, m;
   int b, L, h;  // n, leaves, leaf rows (64, 128 or 256)
+  int arity;    // tree arity K: 2 or 4
   const double *tau_leaf, *tau_node, *d;
   double *B;  // m x nrhs, ldb; rows 0..n-1 receive the solution
   int64_t ldb;
@@ -24,8 +25,9 @@ struct LsbProb {
 // Q^T applied to B by the leaf reflectors: one wave per (problem, leaf, rhs)
 // item {problem, leaf, rhs, 0}.
 hipError_t launch_lsb_leaves(const LsbProb *probs, const int4 *items, int nitems, hipStream_t s);
-// By the node reflectors of one tree level: item {problem, left slot, right
-// slot, rhs}; levels must run bottom-up, after the leaves.
+// By the node reflectors of one tree level: item {problem, survivor slot g,
+// stride s, rhs} (members g + t s, t < K, present below L); levels must run
+// bottom-up, after the leaves.
 hipError_t launch_lsb_nodes(const LsbProb *probs, const int4 *items, int nitems, hipStream_t s);
 // x = R^-1 D (Q_impl^T b)(0:n) in place, and the status pair of each item
 // {problem, rhs}: status[2 (status0 + rhs) + 0] = 1 + first j with R_jj == 0

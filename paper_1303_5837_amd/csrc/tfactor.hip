@@ -35,8 +35,11 @@ __device__ constexpr void block_pair(int p, int &a, int &c) {
 }
 
 // blockIdx.x < L: leaf blockIdx.x (unit lower-trapezoidal Y of h rows);
-// otherwise node blockIdx.x - L, whose reflectors are [I; V] with V upper
-// triangular (the identity adds nothing off the diagonal of G).
+// otherwise tree node id blockIdx.x - L = g + s (survivor g, stride s = K^j
+// the largest power of the arity dividing the id, whose quotient digit is
+// then 1; other ids are not nodes), whose reflectors are [I; V_1; ...;
+// V_{cnt-1}] with every V_t upper triangular over member g + t s (the
+// identity adds nothing off the diagonal of G = sum_t V_t^T V_t).
 template <int NQ>
 __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
   constexpr int NP = NQ * (NQ + 1) / 2;  // block pairs
@@ -45,12 +48,20 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
   const bool is_leaf = (int)blockIdx.x < f.L;
   const int idx = is_leaf ? (int)blockIdx.x : (int)blockIdx.x - f.L;
   if (!is_leaf && idx == 0) return;
+  const int K = f.arity;
+  int s = 1;  // node: stride of its level, and its survivor g
+  if (!is_leaf) {
+    while (idx % (K * s) == 0) s *= K;
+    if ((idx / s) % K != 1) return;  // not a node id
+  }
+  const int g0 = idx - s;  // a node's survivor
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t row0 = (int64_t)idx * f.h;
-  const int nch = is_leaf ? (f.h + 63) / 64 : 1;
+  // leaf: 64-row chunks of Y; node: one chunk per eliminated member (its V_t)
+  const int nch = is_leaf ? (f.h + 63) / 64 : min(K, (f.L - g0 + s - 1) / s) - 1;
   const bool vec_ok = (((uintptr_t)f.Y & 15) == 0) && (f.ldy % 2 == 0);
   if (tid < kMaxB) {
     const double *tau = is_leaf ? f.tau_leaf : f.tau_node;
@@ -65,7 +76,12 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
       if (c < nch) stage_load<kLeafY>(st[c], f.Y, f.ldy, row0 + 64 * c, row0, f.m, f.b, vec_ok, tid);
     stage_fix<kLeafY>(st[0], 0, tid);
   } else {
-    stage_load<kNodeV>(st[0], f.Y, f.ldy, row0, row0, f.m, f.b, vec_ok, tid);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nch) {
+        const int64_t r = (int64_t)(g0 + (c + 1) * s) * f.h;
+        stage_load<kNodeV>(st[c], f.Y, f.ldy, r, r, f.m, f.b, vec_ok, tid);
+      }
     stage_fix<kNodeV>(st[0], 0, tid);
   }
   stage_store(st[0], sm.buf[0], tid);
@@ -85,15 +101,19 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
       block_pair<NQ>(p, a, cc);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
-        // slabs that hold only zeros of both blocks are skipped
-        if (c == 0 && (is_leaf ? tt < cc : tt > a)) continue;
+        // slabs that hold only zeros of both blocks are skipped (a leaf's
+        // top chunk is unit lower trapezoidal, every V_t upper triangular)
+        if (is_leaf ? (c == 0 && tt < cc) : tt > a) continue;
         const f64x4 ya = lds_col4(ys, 16 * a + li, 16 * tt + 4 * lk);
         const f64x4 yc = lds_col4(ys, 16 * cc + li, 16 * tt + 4 * lk);
 #pragma unroll
         for (int r = 0; r < 4; ++r) g[q] = mfma16x16x4(ya[r], yc[r], g[q]);
       }
     }
-    if (c + 1 < 4 && c + 1 < nch) stage_store(st[c + 1 < 4 ? c + 1 : 3], sm.buf[(c + 1) & 1], tid);
+    if (c + 1 < 4 && c + 1 < nch) {
+      if (!is_leaf) stage_fix<kNodeV>(st[c + 1 < 4 ? c + 1 : 3], 0, tid);  // each V_t is a triangle
+      stage_store(st[c + 1 < 4 ? c + 1 : 3], sm.buf[(c + 1) & 1], tid);
+    }
     __syncthreads();
   }
   // strictly upper G into buffer 0: register r of lane (li, lk) of pair (a, c)
@@ -128,6 +148,7 @@ hipError_t launch_form_t_nq(const FormTParams &f, hipStream_t s) {
 
 hipError_t launch_form_t(const FormTParams &f, hipStream_t s) {
   if (f.b < 1 || f.b > kMaxB || f.L < 1 || f.h < 1) return hipErrorInvalidValue;
+  if (f.arity != 2 && f.arity != 4) return hipErrorInvalidValue;
   switch ((f.b + 15) / 16) {
     case 1: return launch_form_t_nq<1>(f, s);
     case 2: return launch_form_t_nq<2>(f, s);

@@ -8,8 +8,9 @@
 // products around a small triangular one, run on FP64 MFMA:
 //
 //   leaf   (rows of leaf i, h x 64 tile):  W = Y_i^T C_i,  W <- T_i^T W,  C_i -= Y_i W
-//   node   (top b rows of the two leaves): W = C_1 + V^T C_2,  W <- T^T W,
-//                                          C_1 -= W,  C_2 -= V W
+//   node   (top b rows of the node's members, survivor 0 and eliminated
+//           members t = 1 .. cnt-1, cnt <= arity K):
+//           W = C_0 + sum_t V_t^T C_t,  W <- T^T W,  C_0 -= W,  C_t -= V_t W
 //
 // (T instead of T^T for Q C.)  One workgroup of four waves updates the rows
 // of one leaf on one 32-column tile: wave (cg, rh) owns columns
@@ -42,6 +43,30 @@ constexpr int kUThreads = 256;  // four waves: wave = column group cg (0..1) + 2
 struct UpdSmem {
   alignas(32) double buf[2][kMaxB * kLdb];  // reflector chunks, V, T; a free one holds the W partials
 };
+
+// LDS of the kernels that apply tree nodes of arity K > 2 with every V_t
+// resident (136 KiB for K = 4, one workgroup per CU): buffers 0 .. K-2 hold
+// V_1 .. V_{K-1}, buffer K-1 the W partials and then T; a leaf update uses
+// buffers 0 and 1 (the layout of UpdSmem).
+template <int K>
+struct UpdSmemWide {
+  alignas(32) double buf[K][kMaxB * kLdb];
+  __device__ UpdSmem &leaf() { return *reinterpret_cast<UpdSmem *>(this); }
+};
+
+template <int K>
+struct NodeSmem {
+  using type = UpdSmemWide<K>;
+};
+template <>
+struct NodeSmem<2> {
+  using type = UpdSmem;
+};
+// Workgroups per CU of a kernel that applies tree nodes of arity K.
+template <int K>
+constexpr int node_wgs_per_cu() {
+  return K == 2 ? 2 : 1;
+}
 
 // Partial W of (row half, column group, block, lane) in a free staging buffer
 // (2 x 2 x 4 x 64 f64x4 = 32 KiB fits in one).
@@ -214,6 +239,131 @@ __device__ __forceinline__ void node_update(const UpdateParams &u, int left, int
   __syncthreads();  // LDS buffers free again
 }
 
+// The same for a node of up to K members (survivor g, members g + t s,
+// t < cnt), K > 2, with every V_t staged once into its own LDS buffer (the
+// next one, then T, loading into registers while the previous is stored), so
+// that both products with it read LDS: W = C_0 + sum_t V_t^T C_t from the
+// two row halves' partial sums (exchanged in buffer K-1, which then takes T),
+// then C_0 -= W and C_t -= V_t W.  Members absent from the node (cnt < K) are
+// skipped member by member (a uniform branch).
+template <int NQ, bool TRANS, int K>
+__device__ __forceinline__ void node_update_k(const UpdateParams &u, int g, int s, int cnt, int tile,
+                                              UpdSmemWide<K> &sm, bool vec_ok) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int cg = wave & 1, rh = wave >> 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int pl = pi16(li);
+  const int64_t col = (int64_t)tile * kUpdTile + 16 * cg + li;
+  const bool colok = col < u.k;
+  auto row_of = [&](int t) { return (int64_t)(g + t * s) * u.h; };
+  StageSplit<kUThreads> st;
+  stage_load_split<kNodeV>(st, u.Y, u.ldy, row_of(1), row_of(1) + 32, 0, 32, u.m, u.b, vec_ok, tid);
+  f64x4 c[K][2];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    if (t >= cnt) break;
+    const int64_t rt = row_of(t), mt = min<int64_t>(u.m, rt + u.b);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      if (2 * rh + x < NQ) c[t][x] = load_slab(u.C, u.ldc, rt + 16 * (2 * rh + x) + 4 * lk, col, mt, colok, vec_ok);
+  }
+#pragma unroll
+  for (int t = 1; t < K; ++t) {
+    if (t >= cnt) break;
+    stage_fix_split<kNodeV>(st, 0, 32, tid);
+    stage_store_split(st, sm.buf[t - 1], tid);
+    if (t + 1 < cnt)
+      stage_load_split<kNodeV>(st, u.Y, u.ldy, row_of(t + 1), row_of(t + 1) + 32, 0, 32, u.m, u.b, vec_ok, tid);
+    else
+      stage_load_split<kDense>(st, u.T_node + (int64_t)(g + s) * 64 * 64, 64, 0, 0, 0, 0, 0, 0, true, tid);
+  }
+  __syncthreads();
+  // partial W over this wave's slabs: sum_t V_t(slab)^T C_t(slab), then its own slabs of C_0
+  f64x4 w[NQ];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) w[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 1; t < K; ++t) {
+    if (t >= cnt) break;
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int t2 = 2 * rh + x;
+        if (t2 > a) continue;  // V upper triangular (also skips t2 >= NQ)
+        const f64x4 v = lds_col4(sm.buf[t - 1], 16 * a + pl, 16 * t2 + 4 * lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(v[r], c[t][x][r], w[a]);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < NQ; ++a)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      if (2 * rh + x == a) w[a] += c[0][x];
+  exchange_w<NQ>(w, sm.buf[K - 1]);
+  __syncthreads();  // partials read: buffer K-1 takes T
+  stage_store_split(st, sm.buf[K - 1], tid);
+  __syncthreads();
+  apply_t_lds<NQ, TRANS>(sm.buf[K - 1], w);
+  // C_0 -= W';  C_t -= V_t W'
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+      if (2 * rh + x == a) c[0][x] -= w[a];
+#pragma unroll
+  for (int t = 1; t < K; ++t) {
+    if (t >= cnt) break;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const int t2 = 2 * rh + x;
+      if (t2 >= NQ) continue;
+      f64x4 acc = c[t][x];
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) {
+        if (a < t2) continue;
+        const f64x4 v = lds_row4(sm.buf[t - 1], 16 * t2 + pl, 16 * a + 4 * lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc = mfma16x16x4(-v[r], w[a][r], acc);
+      }
+      c[t][x] = acc;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    if (t >= cnt) break;
+    const int64_t rt = row_of(t), mt = min<int64_t>(u.m, rt + u.b);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+      if (2 * rh + x < NQ) store_slab(u.C, u.ldc, rt + 16 * (2 * rh + x) + 4 * lk, col, mt, colok, vec_ok, c[t][x]);
+  }
+  __syncthreads();  // LDS buffers free again
+}
+
+// Node update of the group of survivor g at stride s with cnt members.
+template <int NQ, bool TRANS, int K>
+__device__ __forceinline__ void node_update_grp(const UpdateParams &u, int g, int s, int cnt, int tile,
+                                                typename NodeSmem<K>::type &sm, bool vec_ok) {
+  if constexpr (K == 2)
+    node_update<NQ, TRANS>(u, g, g + s, tile, sm, vec_ok);
+  else
+    node_update_k<NQ, TRANS, K>(u, g, s, cnt, tile, sm, vec_ok);
+}
+
+template <int K>
+__device__ __forceinline__ UpdSmem &leaf_smem(typename NodeSmem<K>::type &sm) {
+  if constexpr (K == 2)
+    return sm;
+  else
+    return sm.leaf();
+}
+
+// Members present in the group of survivor g at stride s.
+__device__ __forceinline__ int group_members(int g, int s, int K, int L) { return min(K, (L - g + s - 1) / s); }
+
 // Rows 0..b-1 of this workgroup's tile scaled by D (any thread mapping; the
 // caller orders it after the tile's last update).
 __device__ __forceinline__ void scale_top_rows(const UpdateParams &u, int tile) {
@@ -382,144 +532,163 @@ __global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
   leaf_update<NQ, RT, TRANS>(u, leaf, tile, sm);
 }
 
-// Q^T leaf updates of two neighbouring leaves (2p, 2p + 1) on one tile, then
-// the first tree level's node over them (its rows were just written by this
-// workgroup, so no other workgroup is involved): one workgroup per (pair,
-// tile), and the level launches start at the second level.
-template <int NQ, int RT>
-__global__ void __launch_bounds__(kUThreads, 2) leaf_pair_kernel(UpdateParams u) {
+// Q^T leaf updates of the K neighbouring leaves of one first-level group
+// (leaves g .. g + K - 1) on one tile, then that group's node (its rows were
+// just written by this workgroup, so no other workgroup is involved): one
+// workgroup per (group, tile), and the level launches start at the second
+// level.
+template <int NQ, int RT, int K>
+__global__ void __launch_bounds__(kUThreads, 2) leaf_group_kernel(UpdateParams u) {
+  static_assert(K == 2, "wider nodes are applied by their own level launches");
   __shared__ UpdSmem sm;
-  const int npair = (u.L + 1) / 2;
-  const int pr = blockIdx.x % npair;
-  const int tile = blockIdx.x / npair;
-  leaf_update<NQ, RT, true>(u, 2 * pr, tile, sm);
-  if (2 * pr + 1 < u.L) {
-    leaf_update<NQ, RT, true>(u, 2 * pr + 1, tile, sm);  // ends with a barrier: both leaves' C stored
-    const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
-    node_update<NQ, true>(u, 2 * pr, 2 * pr + 1, tile, sm, vec_ok);
+  const int ngroups = (u.L + K - 1) / K;
+  const int gi = blockIdx.x % ngroups;
+  const int tile = blockIdx.x / ngroups;
+  const int g = K * gi;
+  const int cnt = min(K, u.L - g);
+  const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
+  leaf_update<NQ, RT, true>(u, g, tile, sm);  // each ends with a barrier: the leaf's C stored
+  if constexpr (K == 2) {
+    if (g + 1 < u.L) {
+      leaf_update<NQ, RT, true>(u, g + 1, tile, sm);
+      node_update<NQ, true>(u, g, g + 1, tile, sm, vec_ok);
+    }
   }
 }
 
-template <int NQ, bool TRANS>
-__global__ void __launch_bounds__(kUThreads, 2) node_level_kernel(UpdateParams u) {
-  __shared__ UpdSmem sm;
-  // nodes of this level: ids half, 3*half, 5*half, ... < L
-  const int half = 1 << (u.level - 1);
-  const int per = (u.L + half - 1) / (2 * half) + 1;
-  const int nn = blockIdx.x % per;
+// Every node of tree level u.stride = s on every tile: workgroup (group i,
+// tile), group survivor g = K s i, for the groups with two or more members.
+template <int NQ, bool TRANS, int K>
+__global__ void __launch_bounds__(kUThreads, node_wgs_per_cu<K>()) node_level_kernel(UpdateParams u) {
+  __shared__ typename NodeSmem<K>::type sm;
+  const int s = u.stride;
+  const int per = (u.L - s + K * s - 1) / (K * s);
+  const int gi = blockIdx.x % per;
   const int tile = blockIdx.x / per;
-  const int node = half + 2 * half * nn;
-  if (node >= u.L) return;
+  const int g = K * s * gi;
+  const int cnt = group_members(g, s, K, u.L);
+  if (cnt < 2) return;
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
-  node_update<NQ, TRANS>(u, node - half, node, tile, sm, vec_ok);
+  node_update_grp<NQ, TRANS, K>(u, g, s, cnt, tile, sm, vec_ok);
 }
 
 __global__ void scale_rows_kernel(UpdateParams u) { scale_top_rows(u, blockIdx.x); }
 
-// Last-arriver ticket on node `node`; true when this workgroup arrived second
-// (and performs the node's update).  Publishes this workgroup's stores to C
-// before the ticket and acquires the partner's after it.
-__device__ __forceinline__ bool arrive(unsigned *tickets, int node, int &flag) {
+// Last-arriver ticket on node `node` of cnt members; true for the workgroup
+// that arrives last (and performs the node's update).  Publishes this
+// workgroup's stores to C before the ticket and acquires the other members'
+// after it; the last arriver leaves the counter at zero.
+__device__ __forceinline__ bool arrive(unsigned *tickets, int node, int cnt, int &flag) {
   fence_release();
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned old = ticket_add(tickets + node);
-    flag = (int)old;
-    if (old == 1u) ticket_clear(tickets + node);
+    const bool last = old + 1u == (unsigned)cnt;
+    flag = last ? 1 : 0;
+    if (last) ticket_clear(tickets + node);
   }
   __syncthreads();
-  const bool second = flag == 1;
-  if (second) fence_acquire();
-  return second;
+  const bool last = flag == 1;
+  if (last) fence_acquire();
+  return last;
 }
 
 // Q^T of one panel on a few tiles (at most kTreeTiles, e.g. the next panel's
 // columns), the whole tree in one launch: workgroup (leaf i, tile t) updates
-// leaf i on tile t, then climbs that tile's binary tree; below every node the second workgroup to arrive (an
-// agent-scope ticket) performs the node's update, the first one exits.  The
-// pairing is fixed by index, so the result does not depend on arrival order.
-// The workgroup that completes the root applies D.
-template <int NQ, int RT>
-__global__ void __launch_bounds__(kUThreads, 2) qt_tree_tile_kernel(UpdateParams u) {
-  __shared__ UpdSmem sm;
+// leaf i on tile t, then climbs that tile's tree; below every node the last of
+// its members' workgroups to arrive (an agent-scope ticket) performs the
+// node's update, the others exit.  The grouping is fixed by index, so the
+// result does not depend on arrival order.  The workgroup that completes the
+// root applies D.
+template <int NQ, int RT, int K>
+__global__ void __launch_bounds__(kUThreads, node_wgs_per_cu<K>()) qt_tree_tile_kernel(UpdateParams u) {
+  __shared__ typename NodeSmem<K>::type sm;
   __shared__ int flag;
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
   const int leaf = blockIdx.x % u.L;
   const int tile = blockIdx.x / u.L;
   unsigned *tickets = u.tickets + (int64_t)tile * u.L;  // each tile climbs its own tree
-  leaf_update<NQ, RT, true>(u, leaf, tile, sm);
+  leaf_update<NQ, RT, true>(u, leaf, tile, leaf_smem<K>(sm));
   int rt = leaf;  // root of the subtree this workgroup holds
-  for (int half = 1; half < u.L; half <<= 1) {
-    if ((rt & (2 * half - 1)) == 0) {  // left child at this level
-      const int partner = rt + half;
-      if (partner >= u.L) continue;      // no sibling: pass through
-      if (!arrive(tickets, partner, flag)) return;
-      node_update<NQ, true>(u, rt, partner, tile, sm, vec_ok);
-    } else {  // right child: node id rt, left sibling rt - half
-      const int left = rt - half;
-      if (!arrive(tickets, rt, flag)) return;
-      node_update<NQ, true>(u, left, rt, tile, sm, vec_ok);
-      rt = left;
-    }
+  for (int s = 1; s < u.L; s *= K) {
+    const int g = rt - rt % (K * s);  // survivor of rt's group at this level
+    const int cnt = group_members(g, s, K, u.L);
+    if (cnt < 2) continue;  // alone: pass through
+    if (!arrive(tickets, g + s, cnt, flag)) return;
+    node_update_grp<NQ, true, K>(u, g, s, cnt, tile, sm, vec_ok);
+    rt = g;
   }
   scale_top_rows_own<NQ>(u, tile);
 }
 
-template <int NQ, int RT>
+template <int NQ, int RT, int K>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   if (u.tickets && u.tiles <= kTreeTiles && u.L > 1) {
-    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
+    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT, K>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
     return hipGetLastError();
   }
-  // leaf pairs with the first level, then the tree bottom-up (one launch per
-  // level, nodes of a level in parallel), then D
-  hipLaunchKernelGGL((leaf_pair_kernel<NQ, RT>), dim3((u.L + 1) / 2 * u.tiles), dim3(kUThreads), 0, s, u);
-  for (int lev = 2; (1 << (lev - 1)) < u.L; ++lev) {
+  // binary trees: leaf pairs with the first level, then the tree bottom-up (one
+  // launch per level, nodes of a level in parallel), then D.  Wider nodes: one
+  // workgroup per leaf (short workgroups, so that the concurrent panel chain
+  // reaches free CUs sooner), then every level by its own launch.
+  int st0 = 1;
+  if constexpr (K == 2) {
+    hipLaunchKernelGGL((leaf_group_kernel<NQ, RT, K>), dim3((u.L + K - 1) / K * u.tiles), dim3(kUThreads), 0, s, u);
+    st0 = K;
+  } else {
+    hipLaunchKernelGGL((leaf_kernel<NQ, RT, true>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
+  }
+  for (int st = st0; st < u.L; st *= K) {
     UpdateParams v = u;
-    v.level = lev;
-    const int half = 1 << (lev - 1);
-    const int per = (u.L + half - 1) / (2 * half) + 1;
-    hipLaunchKernelGGL((node_level_kernel<NQ, true>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
+    v.stride = st;
+    const int per = (u.L - st + K * st - 1) / (K * st);
+    hipLaunchKernelGGL((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
   }
   hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
   return hipGetLastError();
 }
 
-template <int NQ, int RT>
+template <int NQ, int RT, int K>
 hipError_t launch_qn_t(const UpdateParams &u, hipStream_t s) {
   hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
-  int levels = 0;
-  while ((1 << levels) < u.L) ++levels;
-  for (int lev = levels; lev >= 1; --lev) {
+  int top = 1;  // stride of the top level
+  while (top * K < u.L) top *= K;
+  for (int st = (u.L > 1) ? top : 0; st >= 1; st /= K) {
     UpdateParams v = u;
-    v.level = lev;
-    const int half = 1 << (lev - 1);
-    const int per = (u.L + half - 1) / (2 * half) + 1;
-    hipLaunchKernelGGL((node_level_kernel<NQ, false>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
+    v.stride = st;
+    const int per = (u.L - st + K * st - 1) / (K * st);
+    hipLaunchKernelGGL((node_level_kernel<NQ, false, K>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
   }
   hipLaunchKernelGGL((leaf_kernel<NQ, RT, false>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
   return hipGetLastError();
 }
 
-template <int RT>
+template <int RT, int K>
 hipError_t dispatch_nq(const UpdateParams &u, bool trans, hipStream_t s) {
   switch ((u.b + 15) / 16) {
-    case 1: return trans ? launch_qt_t<1, RT>(u, s) : launch_qn_t<1, RT>(u, s);
-    case 2: return trans ? launch_qt_t<2, RT>(u, s) : launch_qn_t<2, RT>(u, s);
-    case 3: return trans ? launch_qt_t<3, RT>(u, s) : launch_qn_t<3, RT>(u, s);
-    case 4: return trans ? launch_qt_t<4, RT>(u, s) : launch_qn_t<4, RT>(u, s);
+    case 1: return trans ? launch_qt_t<1, RT, K>(u, s) : launch_qn_t<1, RT, K>(u, s);
+    case 2: return trans ? launch_qt_t<2, RT, K>(u, s) : launch_qn_t<2, RT, K>(u, s);
+    case 3: return trans ? launch_qt_t<3, RT, K>(u, s) : launch_qn_t<3, RT, K>(u, s);
+    case 4: return trans ? launch_qt_t<4, RT, K>(u, s) : launch_qn_t<4, RT, K>(u, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int K>
+hipError_t dispatch_k(const UpdateParams &u, bool trans, hipStream_t s) {
+  switch (u.h) {
+    case 64: return dispatch_nq<4, K>(u, trans, s);
+    case 128: return dispatch_nq<8, K>(u, trans, s);
+    case 256: return dispatch_nq<16, K>(u, trans, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t dispatch(const UpdateParams &u, bool trans, hipStream_t s) {
   if (u.b < 1 || u.b > kMaxB || u.L < 1 || u.k < 1 || u.m < 1) return hipErrorInvalidValue;
-  switch (u.h) {
-    case 64: return dispatch_nq<4>(u, trans, s);
-    case 128: return dispatch_nq<8>(u, trans, s);
-    case 256: return dispatch_nq<16>(u, trans, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (u.arity == 2) return dispatch_k<2>(u, trans, s);
+  if (u.arity == 4) return dispatch_k<4>(u, trans, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace

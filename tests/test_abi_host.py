@@ -190,7 +190,9 @@ def test_inner_block_validation_without_device():
     for ib in (8, 24, 48, -16, 128, 1):
         assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, ib, 0))) == 1
     assert _tsqr(10, 20, A, 10, ctypes.byref(caqr.TreeOpts(0, 0, 16, 0))) == 4  # m < n still NOT_SUPPORTED
-    assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, 16, 7))) == 1  # reserved must be 0
+    assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, 16, 7))) == 1  # arity 7 is invalid
+    assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, 16, 4))) == 4  # inner blocks need arity 2
+    assert _tsqr(100, 40, A, 100, ctypes.byref(caqr.TreeOpts(0, 0, 16, 2))) == 1  # valid: the NULL handle fails
     M = (ctypes.c_int64 * 1)(100)
     N = (ctypes.c_int64 * 1)(8)
     P = (ctypes.c_void_p * 1)(A.value)
@@ -214,3 +216,22 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_arity_validation_without_device():
+    """arity: 0 (default), 2 or 4; leaves_per_wg a power of the arity (2 selects
+    the binary tree when arity is left open)."""
+    A = ctypes.c_void_p(0x1000)
+    for ar, lpw in ((0, 0), (2, 1), (2, 2), (2, 4), (4, 1), (4, 4), (0, 2), (0, 4)):
+        assert _tsqr(1000, 40, A, 1000, ctypes.byref(caqr.TreeOpts(0, lpw, 0, ar))) == 1, (ar, lpw)  # NULL handle
+    for ar, lpw in ((3, 0), (8, 0), (-2, 0), (1, 0), (4, 2)):
+        assert _tsqr(1000, 40, A, 1000, ctypes.byref(caqr.TreeOpts(0, lpw, 0, ar))) == 1, (ar, lpw)
+    lib = caqr.library()
+    M = (ctypes.c_int64 * 1)(100)
+    N = (ctypes.c_int64 * 1)(8)
+    P = (ctypes.c_void_p * 1)(A.value)
+    f = ctypes.c_void_p()
+    assert lib.tsqr_factor_batched(None, 1, M, N, P, M, caqr.F64, ctypes.byref(caqr.TreeOpts(0, 4, 0, 4)),
+                                   ctypes.byref(f)) == 1  # valid arity-4 plan: the NULL handle fails
+    assert lib.tsqr_factor_batched(None, 1, M, N, P, M, caqr.F64, ctypes.byref(caqr.TreeOpts(0, 2, 0, 4)),
+                                   ctypes.byref(f)) == 1  # two leaves per workgroup with arity 4: invalid

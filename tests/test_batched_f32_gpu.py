@@ -60,10 +60,10 @@ def test_f32_fixed_plan_against_oracle():
     check32(SIZES, 700, leaf_rows=256, leaves_per_wg=4)
 
 
-@pytest.mark.parametrize("leaf_rows,lpw", [(64, 1), (128, 2), (64, 4)])
-def test_f32_other_plans(leaf_rows, lpw):
+@pytest.mark.parametrize("leaf_rows,lpw,arity", [(64, 1, 4), (128, 2, 2), (64, 4, 4), (256, 1, 2), (128, 4, 2)])
+def test_f32_other_plans(leaf_rows, lpw, arity):
     require_gpu()
-    check32(SIZES[:12], 800 + leaf_rows + lpw, leaf_rows=leaf_rows, leaves_per_wg=lpw)
+    check32(SIZES[:12], 800 + leaf_rows + lpw, leaf_rows=leaf_rows, leaves_per_wg=lpw, arity=arity)
 
 
 def test_f32_alone_equals_in_batch():
@@ -126,8 +126,8 @@ def test_f32_tuner_and_default_plans():
     caqr.tune_batched(dtype=torch.float32)
     sizes = [(300, 8), (5000, 16), (40000, 64), (70000, 32), (100, 64)]
     for m, n in sizes:
-        hr, lpw = caqr.batch_plan_for(m, n, dtype=torch.float32)
-        assert hr in (64, 128, 256) and lpw in (1, 2, 4)
+        hr, lpw, ar = caqr.batch_plan_for(m, n, dtype=torch.float32)
+        assert hr in (64, 128, 256) and (ar, lpw) in ((2, 1), (2, 2), (2, 4), (4, 1), (4, 4))
     hosts, devs = make32(sizes, 980)
     B = caqr.tsqr_batched(devs)
     torch.cuda.synchronize()

@@ -31,7 +31,7 @@ def make(sizes, seed):
 
 def single(A, plan):
     d = caqr.fortran(A)
-    F = caqr.tsqr(d, leaf_rows=plan[0], leaves_per_wg=plan[1])
+    F = caqr.tsqr(d, leaf_rows=plan[0], leaves_per_wg=plan[1], arity=plan[2])
     torch.cuda.synchronize()
     return d.cpu().numpy(), F.signs()
 
@@ -60,10 +60,10 @@ def test_fixed_plan_matches_single_and_oracle():
     check_batch(SIZES, 300, leaf_rows=256, leaves_per_wg=4)
 
 
-@pytest.mark.parametrize("leaf_rows,lpw", [(64, 1), (128, 2), (64, 4)])
-def test_other_plans(leaf_rows, lpw):
+@pytest.mark.parametrize("leaf_rows,lpw,arity", [(64, 1, 4), (128, 2, 2), (64, 4, 4), (256, 1, 2), (128, 4, 2)])
+def test_other_plans(leaf_rows, lpw, arity):
     require_gpu()
-    check_batch(SIZES[:12], 400 + leaf_rows + lpw, leaf_rows=leaf_rows, leaves_per_wg=lpw)
+    check_batch(SIZES[:12], 400 + leaf_rows + lpw, leaf_rows=leaf_rows, leaves_per_wg=lpw, arity=arity)
 
 
 def test_default_plans():
@@ -76,8 +76,8 @@ def test_tuner_plans_are_used():
     caqr.tune_batched()
     sizes = [(300, 8), (5000, 16), (40000, 64), (70000, 32), (100, 64)]
     for m, n in sizes:
-        hr, lpw = caqr.batch_plan_for(m, n)
-        assert hr in (64, 128, 256) and lpw in (1, 2, 4)
+        hr, lpw, ar = caqr.batch_plan_for(m, n)
+        assert hr in (64, 128, 256) and (ar, lpw) in ((2, 1), (2, 2), (2, 4), (4, 1), (4, 4))
     hosts, devs = make(sizes, 600)
     B = caqr.tsqr_batched(devs)
     torch.cuda.synchronize()

@@ -28,22 +28,25 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("arity", [4, 2])
 @pytest.mark.parametrize("m,n,nb,h", CASES)
-def test_r_matches_oracle(m, n, nb, h):
+def test_r_matches_oracle(m, n, nb, h, arity):
     require_gpu()
-    banner(f"caqr parity m={m} n={n} nb={nb} leaf_rows={h}")
+    banner(f"caqr parity m={m} n={n} nb={nb} leaf_rows={h} arity={arity}")
     A = inputs.gaussian(m, n, 2000 + m + n)
-    F, R = caqr_gpu(A, nb=nb, leaf_rows=h)
+    F, R = caqr_gpu(A, nb=nb, leaf_rows=h, arity=arity)
+    assert F.info().arity == arity
     oracle.set_threads(16)
     Rref = oracle.qr_r(A)
     assert np.all(np.diag(R) >= 0)
     assert oracle.rel_fro(R, Rref) <= TOL_R
 
 
-def test_invariants():
+@pytest.mark.parametrize("arity", [4, 2])
+def test_invariants(arity):
     require_gpu()
     A = inputs.gaussian(1500, 1100, 91)
-    F, R = caqr_gpu(A)
+    F, R = caqr_gpu(A, arity=arity)
     Q = q_thin(F)
     assert oracle.factorization_error(A, Q, R) <= 1e-13
     assert oracle.orthogonality_error(Q) <= 1e-13
@@ -62,15 +65,16 @@ def test_determinism():
 TALL = [(40000, 200), (65536, 1024)]
 
 
+@pytest.mark.parametrize("arity", [4, 2])
 @pytest.mark.parametrize("m,n", TALL)
-def test_tall_caqr_level_path(m, n):
+def test_tall_caqr_level_path(m, n, arity):
     """R against the oracle, Q_thin^T C (unique for full-rank A) against the
     oracle's, the round trip Q (Q^T C) = C, and Q^T A = [R; 0]."""
     require_gpu()
-    banner(f"tall caqr parity m={m} n={n}")
+    banner(f"tall caqr parity m={m} n={n} arity={arity}")
     A = inputs.gaussian(m, n, 2100 + n)
     dA0 = caqr.fortran(A)
-    F, R = caqr_gpu(A)
+    F, R = caqr_gpu(A, arity=arity)
     assert F.info().leaves_panel0 >= 128
     oracle.set_threads(16)
     f = oracle.qr(A)

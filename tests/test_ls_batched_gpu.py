@@ -59,15 +59,15 @@ def test_batched_ls_against_oracle_and_plain():
         assert oracle.rel_fro(Xs[i], Xp.cpu().numpy()) <= 1e-12
 
 
-@pytest.mark.parametrize("leaf_rows,lpw", [(64, 1), (128, 2), (256, 4)])
-def test_batched_ls_plans(leaf_rows, lpw):
+@pytest.mark.parametrize("leaf_rows,lpw,arity", [(64, 1, 4), (128, 2, 2), (256, 4, 4), (64, 4, 2)])
+def test_batched_ls_plans(leaf_rows, lpw, arity):
     require_gpu()
     mix = MIX[:7]
-    As, Bs, Xs, info = run(mix, 8200 + leaf_rows + lpw, leaf_rows=leaf_rows, leaves_per_wg=lpw)
+    As, Bs, Xs, info = run(mix, 8200 + leaf_rows + lpw, leaf_rows=leaf_rows, leaves_per_wg=lpw, arity=arity)
     for i, (m, n, k) in enumerate(mix):
         assert info[i] == (0, 0)
         Xref, _ = oracle.ls(As[i], Bs[i])
-        assert oracle.rel_fro(Xs[i], Xref) <= 1e-11, (m, n, k, leaf_rows, lpw)
+        assert oracle.rel_fro(Xs[i], Xref) <= 1e-11, (m, n, k, leaf_rows, lpw, arity)
 
 
 def test_batched_ls_conditioned_consistent():

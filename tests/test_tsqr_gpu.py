@@ -1,4 +1,4 @@
-"""TSQR (one panel, binary reduction tree) on the GPU vs the oracle.
+"""TSQR (one panel, reduction tree of arity 2 or 4) on the GPU vs the oracle.
 
 Bars: ||R - R_oracle||_F / ||R_oracle||_F <= 1e-11 (FP64), ||A - QR||/||A|| and
 ||I - Q^T Q|| <= 1e-13, and the exact identities of the method (tree shape and
@@ -55,9 +55,9 @@ def test_config0_invariants_and_apply_q():
     require_gpu()
     banner("tsqr 4096x32 invariants")
     A = inputs.gaussian(4096, 32, inputs.SEEDS["tsqr_4096x32"])
-    F, R = tsqr_gpu(A)
+    F, R = tsqr_gpu(A, arity=2)  # this configuration's binary tree over 16 leaves
     info = F.info()
-    assert info.leaves_panel0 == 16 and info.depth_panel0 == 4
+    assert info.leaves_panel0 == 16 and info.depth_panel0 == 4 and info.arity == 2
     Q = q_thin(F)
     assert oracle.factorization_error(A, Q, R) <= TOL_INV
     assert oracle.orthogonality_error(Q) <= TOL_INV
@@ -82,7 +82,8 @@ def test_config0_invariants_and_apply_q():
     assert np.abs(QtA[32:]).max() <= 1e-12 * np.abs(A).max() * 64
 
 
-def test_grouping_does_not_change_anything():
+@pytest.mark.parametrize("arity,lpws", [(2, (1, 2, 4)), (4, (1, 4))])
+def test_grouping_does_not_change_anything(arity, lpws):
     """leaves_per_wg only moves tree levels between a workgroup and the device: bitwise equal.
     At 40000 rows (313 leaves of 128) one and two leaves per workgroup finish the tree by one
     launch per level, four by ticket climbs: the two device-level schemes agree bitwise too."""
@@ -90,16 +91,62 @@ def test_grouping_does_not_change_anything():
     for m, seed in ((9000, 77), (40000, 76)):
         A = inputs.gaussian(m, 40, seed)
         outs = []
-        for lpw in (1, 2, 4):
-            F, R = tsqr_gpu(A, leaf_rows=128, leaves_per_wg=lpw)
+        for lpw in lpws:
+            F, R = tsqr_gpu(A, leaf_rows=128, leaves_per_wg=lpw, arity=arity)
+            assert F.info().arity == arity
             outs.append(factored(F))
-        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2]), m
+        for o in outs[1:]:
+            assert np.array_equal(outs[0], o), (m, arity)
+
+
+# (m, n, leaf_rows, leaves_per_wg): leaf counts that are and are not powers of
+# four, groups with 2 and 3 members at the end of a level, one leaf, ticket
+# climbs and level launches (128 or more workgroups)
+ARITY_CASES = [(4096, 32, 256, 1), (1000, 7, 256, 1), (1280, 20, 256, 1), (1536, 64, 256, 1), (2600, 48, 128, 4),
+               (300, 64, 64, 1), (257, 33, 256, 4), (100, 64, 256, 1), (40000, 17, 256, 4), (40000, 17, 256, 1),
+               (70000, 64, 64, 1), (33000, 64, 128, 4)]
+
+
+@pytest.mark.parametrize("m,n,h,lpw", ARITY_CASES)
+def test_arity4_against_oracle_and_binary(m, n, h, lpw):
+    """Arity-4 trees: R against the oracle, against the binary tree's R (the
+    same R of a full-rank A: tree independence), Q's invariants and the Q^T / Q
+    round trip."""
+    require_gpu()
+    banner(f"arity-4 tsqr m={m} n={n} leaf_rows={h} lpw={lpw}")
+    A = inputs.gaussian(m, n, 1500 + m + n)
+    F, R = tsqr_gpu(A, leaf_rows=h, leaves_per_wg=lpw, arity=4)
+    assert F.info().arity == 4
+    L = -(-m // h)
+    depth = 0
+    while 4 ** depth < L:
+        depth += 1
+    assert F.info().depth_panel0 == depth
+    Rref = oracle.qr_r(A)
+    assert np.all(np.diag(R) >= 0)
+    assert oracle.rel_fro(R, Rref) <= TOL_R
+    R2 = tsqr_gpu(A, leaf_rows=h, leaves_per_wg=1, arity=2)[1]
+    assert oracle.rel_fro(R, R2) <= TOL_INV
+    if m * n <= 400000:
+        Q = q_thin(F)
+        assert oracle.factorization_error(A, Q, R) <= TOL_INV
+        assert oracle.orthogonality_error(Q) <= TOL_INV
+    import torch
+
+    from paper_1303_5837_amd import caqr
+
+    C0 = np.random.default_rng(6).standard_normal((m, 3))
+    C = caqr.fortran(C0)
+    F.apply_q(C, caqr.OP_T)
+    F.apply_q(C, caqr.OP_N)
+    torch.cuda.synchronize()
+    assert oracle.rel_fro(C.cpu().numpy(), C0) <= 1e-14
 
 
 def test_leaf_height_independence():
     require_gpu()
     A = inputs.gaussian(12345, 50, 78)
-    Rs = [tsqr_gpu(A, leaf_rows=h)[1] for h in (64, 128, 256)]
+    Rs = [tsqr_gpu(A, leaf_rows=h, arity=k)[1] for h in (64, 128, 256) for k in (2, 4)]
     for R in Rs[1:]:
         assert oracle.rel_fro(R, Rs[0]) <= 1e-13
 
