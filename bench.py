@@ -337,6 +337,61 @@ def inner_block_line(dev, n, reps=3):
     return out
 
 
+def mixed_ls_line(m=65536, n=1024, kappas=(1e2, 1e4, 1e6), reps=5):
+    """Mixed-precision least squares on A = U diag(s) V^T (U, V orthonormal
+    factors of seeded Gaussian draws, s geometric from 1 to 1/kappa, ||A||_2 =
+    1), b ~ N(0,1): ls_solve with FP32-MFMA trailing updates and FP64
+    refinement to eta <= 1e-12, against the plain FP64 ls_solve of the same
+    problem; median of `reps` calls each (synchronous calls, host clock; A
+    and b restored outside the timed calls).  Both solves get b stored right
+    after A ([A | b] in one buffer), so both factor [A | b] and get Q^T b from
+    the trailing updates.  eta of both results from its definition with
+    ||A||_2 = 1."""
+    import numpy as np
+    import torch
+
+    from paper_1303_5837_amd import caqr, inputs
+
+    seed = inputs.SEEDS["mixed_ls"]
+    rngs = inputs.substreams(seed, 3)
+    U = torch.as_tensor(np.linalg.qr(rngs[0].standard_normal((m, n)))[0], device="cuda")
+    V = torch.as_tensor(np.linalg.qr(rngs[1].standard_normal((n, n)))[0], device="cuda")
+    b0 = caqr.fortran(rngs[2].standard_normal((m, 1)))
+    out = {"m": m, "n": n, "construction": "A = U diag(s) V^T, s geometric 1 .. 1/kappa; b ~ N(0,1)"}
+    for kappa in kappas:
+        s = torch.as_tensor(inputs.geometric_singular_values(n, kappa), device="cuda")
+        A0 = torch.empty((n, m), dtype=torch.float64, device="cuda").t()
+        A0.copy_((U * s) @ V.t())
+        M = torch.empty((n + 1, m), dtype=torch.float64, device="cuda").t()  # [A | b], column-major
+        A, B = M[:, :n], M[:, n:]
+
+        def eta(X):
+            r = b0 - A0 @ X
+            return float(torch.linalg.norm(A0.t() @ r)) / (float(torch.linalg.norm(X)) + float(torch.linalg.norm(b0)))
+
+        row = {}
+        for label, prec in (("plain_f64", caqr.LS_F64), ("mixed_f32", caqr.LS_MIXED_F32)):
+            ts, info = [], None
+            for it in range(2 + reps):
+                A.copy_(A0)
+                B.copy_(b0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                X, info = caqr.ls_solve(A, B, precision=prec)
+                t1 = time.perf_counter()
+                if it >= 2:
+                    ts.append((t1 - t0) * 1e3)
+            row[label] = {"median_ms": round(float(np.median(ts)), 3), "status": int(info.status),
+                          "eta": eta(X.clone()), "iters": int(info.iters), "fallback": int(info.fallback),
+                          "eta_bound": float(info.eta)}
+        row["speedup_mixed_vs_plain"] = round(row["plain_f64"]["median_ms"] / row["mixed_f32"]["median_ms"], 3)
+        out["kappa_%.0e" % kappa] = row
+        del A0, A, B, M
+    del U, V
+    torch.cuda.empty_cache()
+    return out
+
+
 TSQR_LINES = {"tsqr_1Mx64": (1 << 20, 64), "tsqr_4096x32": (4096, 32)}
 
 
@@ -437,7 +492,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--only", choices=["batched_tsqr", "batched_tsqr_f32", "batched_ls", "served", "tsqr_1Mx64",
-                                       "tsqr_4096x32"],
+                                       "tsqr_4096x32", "mixed_ls"],
                     help="run one secondary workload alone and print its line (for profiling)")
     ap.add_argument("--served-workers", type=int, default=8, help="worker threads of the served stream's server")
     args = ap.parse_args()
@@ -458,7 +513,8 @@ def main():
     if args.only:
         fn = {"batched_tsqr": lambda: batched_line("f64"), "batched_tsqr_f32": lambda: batched_line("f32"),
               "batched_ls": batched_ls_line, "served": lambda: served_lines(workers=args.served_workers),
-              "tsqr_1Mx64": lambda: tsqr_line("tsqr_1Mx64"), "tsqr_4096x32": lambda: tsqr_line("tsqr_4096x32")}[args.only]
+              "tsqr_1Mx64": lambda: tsqr_line("tsqr_1Mx64"), "tsqr_4096x32": lambda: tsqr_line("tsqr_4096x32"),
+              "mixed_ls": mixed_ls_line}[args.only]
         print(json.dumps({args.only: fn()}))
         return
     dev = torch.device("cuda:0")
@@ -563,6 +619,7 @@ def main():
         sec["batched_tsqr_2000_uneven"] = batched_line("f64")
         sec["batched_tsqr_2000_uneven_f32"] = batched_line("f32")
         sec["batched_ls_2000_uneven"] = batched_ls_line()
+        sec["mixed_ls_65536x1024"] = mixed_ls_line()
         sec["served_ls"] = served_line_child(args.served_workers)
         out["secondary"] = sec
 

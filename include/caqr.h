@@ -63,7 +63,7 @@ typedef enum {
   CAQR_ERR_NOT_SUPPORTED = 4, /* valid request outside what is implemented (e.g. m < n) */
   CAQR_ERR_SINGULAR = 5,      /* ls_solve: R has an exactly zero diagonal entry */
   CAQR_ERR_NONFINITE = 6,     /* ls_solve: NaN/Inf in R's diagonal or in the solution */
-  CAQR_ERR_NOT_CONVERGED = 7  /* reserved for iterative refinement */
+  CAQR_ERR_NOT_CONVERGED = 7  /* ls_solve, mixed precision: refinement did not reach its tolerance */
 } caqr_status_t;
 
 typedef enum { CAQR_OP_N = 0, CAQR_OP_T = 1 } caqr_op_t;
@@ -122,14 +122,42 @@ typedef struct {
   int32_t arity;          /* tree arity used (2 or 4) */
 } caqr_factors_info_t;
 
-/* Least-squares options and report. */
+/* Least-squares options and report.
+ *   precision  CAQR_LS_F64 (0): the FP64 solve.  CAQR_LS_MIXED_F32 (1): the
+ *              factorization's trailing-update products with the leaf
+ *              reflectors (Y^T C and Y W) run on FP32 MFMA with FP32
+ *              accumulation, while reflector generation, norms, the tree's
+ *              R combines and node updates, the residuals and every step of
+ *              the refinement stay FP64; the solution is refined in FP64 by
+ *              CGLS on min ||b - A R~^-1 y||, x = R~^-1 y (R~ the computed R
+ *              as a right preconditioner) until the backward-error bound
+ *              ||A^T r|| / (a (a ||x|| + ||b||)) <= tol, a = max(||A||_F /
+ *              sqrt(n), max_j ||A(:, j)||) <= ||A||_2 (so the reported bound
+ *              is at least eta(x)), checked on a recomputed residual.
+ *   max_iter   refinement iterations per right-hand side (0: 30).
+ *   tol        target backward-error bound (0: 1e-12).
+ *   no_fallback  0: when refinement does not reach tol (it stalls or runs out
+ *              of iterations), the problem is solved again in FP64 from A
+ *              and info->fallback is set; 1: return CAQR_ERR_NOT_CONVERGED
+ *              with the last iterate in B.
+ * With n <= 64 there is no trailing update, so the mixed solve is the FP64
+ * one. */
+typedef enum { CAQR_LS_F64 = 0, CAQR_LS_MIXED_F32 = 1 } caqr_ls_precision_t;
+
 typedef struct {
-  int32_t reserved; /* 0 */
+  int32_t precision;   /* caqr_ls_precision_t */
+  int32_t max_iter;    /* 0 = 30 */
+  double tol;          /* 0 = 1e-12 */
+  int32_t no_fallback; /* 0 or 1 */
+  int32_t reserved;    /* 0 */
 } caqr_ls_opts_t;
 
 typedef struct {
-  int32_t status; /* caqr_status_t of the solve (valid after caqr_sync) */
-  int64_t index;  /* first j with R_jj == 0 when status == CAQR_ERR_SINGULAR */
+  int32_t status;   /* caqr_status_t of the solve (valid after caqr_sync) */
+  int64_t index;    /* first j with R_jj == 0 when status == CAQR_ERR_SINGULAR */
+  int32_t iters;    /* mixed precision: refinement iterations (largest over the right-hand sides) */
+  int32_t fallback; /* mixed precision: 1 when the FP64 solve replaced the refined one */
+  double eta;       /* mixed precision: final backward-error bound (largest over the right-hand sides) */
 } caqr_ls_info_t;
 
 /* Argument checks run before the handle is inspected, so every size or
@@ -214,8 +242,12 @@ caqr_status_t caqr_factors_get_signs(caqr_handle_t h, caqr_factors_t F, double *
 /* ------------------------------------------------------- least squares */
 
 /* Solve min ||A x - b|| for each of the nrhs columns of B (m >= n).
- * A (m-by-n, lda) is overwritten by its factorization, B (m-by-nrhs, ldb >=
- * max(1, m)) by Q^T B with the solutions in B(0:n, :).  o may be NULL.
+ * FP64 (o NULL or o->precision == CAQR_LS_F64): A (m-by-n, lda) is
+ * overwritten by its factorization, B (m-by-nrhs, ldb >= max(1, m)) by Q^T B
+ * with the solutions in B(0:n, :).  Mixed precision: A is only read (the
+ * library factors a copy, and the refinement needs A), B(0:n, :) receives
+ * the solutions and the rest of B is left unspecified; the workspace (a copy
+ * of A, the factors and the refinement's vectors) is allocated for the call.
  * The call waits for its stream and returns the numerical status:
  * CAQR_ERR_SINGULAR (info->index = first j with R_jj == 0) or
  * CAQR_ERR_NONFINITE (NaN/Inf in R's diagonal or in the solution); info (host

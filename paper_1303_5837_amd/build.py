@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcaqr.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["abi.hip", "panel.hip", "panel_a4.hip", "panel_ib.hip", "panel_batched_f64.hip", "panel_batched_f32.hip",
-           "update.hip", "tfactor.hip", "ls.hip", "serve.hip", "lsb.hip"]
+           "update.hip", "tfactor.hip", "ls.hip", "serve.hip", "lsb.hip", "refine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

@@ -60,12 +60,17 @@ class TraceEntry(ctypes.Structure):
 TRACE_KINDS = {0: "panel", 1: "update_t", 2: "update_n", 3: "form_t", 4: "other", 5: "update_t_levels"}
 
 
+LS_F64, LS_MIXED_F32 = 0, 1
+
+
 class LsOpts(ctypes.Structure):
-    _fields_ = [("reserved", ctypes.c_int32)]
+    _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("no_fallback", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class LsInfo(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("index", ctypes.c_int64)]
+    _fields_ = [("status", ctypes.c_int32), ("index", ctypes.c_int64), ("iters", ctypes.c_int32),
+                ("fallback", ctypes.c_int32), ("eta", ctypes.c_double)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -326,14 +331,23 @@ def caqr(A: torch.Tensor, nb: int = 64, leaf_rows: int = 0, leaves_per_wg: int =
     return Factors(h, f, A)
 
 
-def ls_solve(A: torch.Tensor, B: torch.Tensor, device: int = 0):
-    """Least squares in place: returns (X = B[:n], info); raises CaqrError on a numerical failure."""
+def ls_solve(A: torch.Tensor, B: torch.Tensor, device: int = 0, precision: int = LS_F64, tol: float = 0.0,
+             max_iter: int = 0, fallback: bool = True):
+    """Least squares: returns (X = B[:n], info).  FP64 (default): A and B in
+    place (A factored, B <- Q^T B).  precision=LS_MIXED_F32: A only read,
+    trailing updates on FP32 MFMA and FP64 refinement to the backward-error
+    bound tol (0: 1e-12), falling back to the FP64 solve when it stalls
+    (fallback=False: CAQR_ERR_NOT_CONVERGED instead, status 7).  Raises
+    CaqrError on argument or device errors only."""
     h = handle(device)
     m, n = A.shape
     info = LsInfo()
+    opts = None
+    if precision != LS_F64 or tol or max_iter or not fallback:
+        opts = ctypes.byref(LsOpts(precision, max_iter, tol, 0 if fallback else 1, 0))
     code = _lib().ls_solve(h.ptr, m, n, B.shape[1], ctypes.c_void_p(A.data_ptr()), _ld(A),
-                           ctypes.c_void_p(B.data_ptr()), _ld(B), None, ctypes.byref(info))
-    if code not in (0, 5, 6):
+                           ctypes.c_void_p(B.data_ptr()), _ld(B), opts, ctypes.byref(info))
+    if code not in (0, 5, 6, 7):
         _check(code, "ls_solve")
     return B[:n], info
 

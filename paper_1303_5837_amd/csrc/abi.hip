@@ -18,6 +18,7 @@
 #include "abi_internal.hpp"
 #include "kernels.hpp"
 #include "lsb.hpp"
+#include "refine.hpp"
 
 using namespace caqr;
 
@@ -152,6 +153,7 @@ struct caqr_batch_s {
 struct caqr_factors_s {
   int device = 0;
   int64_t m = 0, n = 0, nb = 0, lda = 0;
+  int64_t ncols = 0;  // columns the trailing updates cover: n, or n + the right-hand sides stored after A
   double *A = nullptr;
   int leaf_rows = 256, lpw = 1;
   int arity = kDefaultArity;  // of every panel's tree
@@ -165,6 +167,7 @@ struct caqr_factors_s {
   size_t limit = 0;
   unsigned *tickets = nullptr;  // lent ticket counters (zero on entry), else the handle's
   bool lookahead = true;        // false: the panel loop on the handle's stream alone
+  bool mixed = false;           // trailing updates' leaf products on FP32 MFMA
 };
 
 namespace {
@@ -286,6 +289,7 @@ caqr_status_t make_factors(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, do
   F->device = h->device;
   F->m = m;
   F->n = n;
+  F->ncols = n;
   F->nb = nb;
   F->lda = lda;
   F->A = A;
@@ -392,6 +396,7 @@ UpdateParams update_params(caqr_handle_t h, caqr_factors_t F, const PanelRec &p,
   u.tiles = ceil_div(k, kUpdTile);
   u.arity = F->arity;
   u.stride = 0;
+  u.f32 = 0;
   u.tickets = nullptr;
   return u;
 }
@@ -460,6 +465,7 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
   // the tickets belong to the handle's stream (panel kernels use them too);
   // tall panels update level by level instead (as their trees are built)
   if (st == h->stream && p.L < kLevelLaunchWgs) u.tickets = F->tickets ? F->tickets : panel_tickets(h);
+  u.f32 = F->mixed ? 1 : 0;
   // the same test launch_apply_qt makes: one tree-climbing launch, or levels
   const bool one_launch = u.tickets && u.tiles <= kTreeTiles && u.L > 1;
   if (forced_fault(h)) return CAQR_ERR_DEVICE;
@@ -489,14 +495,14 @@ caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) 
   for (int idx = 0; idx < P; ++idx) {
     const PanelRec &p = F->panels[idx];
     const int64_t c0 = p.col0 + p.b;
-    const int64_t k = F->n - c0;
+    const int64_t k = F->ncols - c0;
     if (k <= 0) break;
     if (!ahead || idx + 1 >= P) {  // the whole trailing matrix, then the next panel
       if ((st = launch_trailing(h, F, idx, c0, k, h->stream))) return st;
       if (idx + 1 < P && (st = launch_panel(h, F, idx + 1, form_t, h->stream))) return st;
       continue;
     }
-    const int64_t kn = F->panels[idx + 1].b;  // columns of the next panel
+    const int64_t kn = F->panels[idx + 1].b;  // columns of the next panel (never the extra columns)
     if ((st = launch_trailing(h, F, idx, c0, kn, h->stream))) return st;
     const bool wide = k > kn;
     if (wide) {
@@ -574,23 +580,29 @@ bool inner_block_unsupported(const caqr_tree_opts_t *o) {
   return o && o->inner_block && o->inner_block < kNbMax && resolve_arity(o) != 2;
 }
 
+// extra > 0: the `extra` columns stored right after A (same leading
+// dimension) are updated with every panel's Q^T as trailing columns but not
+// factored, so they end as Q^T times themselves (the right-hand sides of a
+// least-squares solve); a single panel then forms its T too.
 caqr_status_t factor_impl(caqr_handle_t h, int64_t m, int64_t n, int64_t nb, double *A, int64_t lda,
                           const caqr_tree_opts_t *opts, caqr_factors_t *F, bool tsqr, void *ws = nullptr,
-                          unsigned *tickets = nullptr) {
+                          unsigned *tickets = nullptr, bool mixed = false, int64_t extra = 0) {
   const int hr = resolve_leaf_rows(opts);
   // default: one leaf per workgroup (every leaf factored in parallel)
   const int lpw = (opts && opts->leaves_per_wg) ? opts->leaves_per_wg : 1;
   DeviceGuard g(h->device);
   caqr_factors_t f = nullptr;
-  caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, resolve_arity(opts), !tsqr, ws, &f);
+  caqr_status_t st = make_factors(h, m, n, nb, A, lda, hr, lpw, resolve_arity(opts), !tsqr || extra > 0, ws, &f);
   if (st) return st;
   f->inner_block = (opts && opts->inner_block < kNbMax) ? opts->inner_block : 0;
   if (tickets) {  // lent counters: no allocation and no second stream
     f->tickets = tickets;
     f->lookahead = false;
   }
+  f->mixed = mixed;
+  f->ncols = n + extra;
   if (n > 0) {
-    st = run_factorization(h, f, !tsqr);
+    st = run_factorization(h, f, !tsqr || extra > 0);
     if (st) {
       caqr_factors_destroy(f);
       return st;
@@ -1053,10 +1065,32 @@ caqr_status_t ls_solve(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, doub
   if (m < 0 || n < 0 || nrhs < 0 || lda < std::max<int64_t>(1, m) || ldb < std::max<int64_t>(1, m))
     return CAQR_ERR_INVALID_VALUE;
   if ((n > 0 && !A) || (nrhs > 0 && !B)) return CAQR_ERR_INVALID_VALUE;
-  if (o && o->reserved) return CAQR_ERR_INVALID_VALUE;
+  if (o && (o->reserved || (o->precision != CAQR_LS_F64 && o->precision != CAQR_LS_MIXED_F32) || o->max_iter < 0 ||
+            !(o->tol >= 0.0) || (o->no_fallback != 0 && o->no_fallback != 1)))
+    return CAQR_ERR_INVALID_VALUE;
   if (m < n) return CAQR_ERR_NOT_SUPPORTED;
   if (n > INT32_MAX || m / std::max<int64_t>(n, 1) > ((int64_t)1 << 40)) return CAQR_ERR_NOT_SUPPORTED;
   if (!h) return CAQR_ERR_INVALID_VALUE;
+  if (o && o->precision == CAQR_LS_MIXED_F32 && n > kNbMax)
+    return caqr::ls_solve_mixed(h, m, n, nrhs, A, lda, B, ldb, *o, info);
+  if (o && o->precision == CAQR_LS_MIXED_F32) {  // no trailing update: the FP64 solve on a copy, A only read
+    double *W = nullptr;
+    if (n > 0 && nrhs > 0) {
+      const size_t bytes = (size_t)m * n * sizeof(double);
+      if (h->ws_limit && bytes > h->ws_limit) return CAQR_ERR_ALLOC;
+      DeviceGuard g(h->device);
+      if (hipMalloc(&W, bytes) != hipSuccess) return CAQR_ERR_ALLOC;
+      if (hipMemcpy2DAsync(W, m * sizeof(double), A, lda * sizeof(double), m * sizeof(double), n,
+                           hipMemcpyDeviceToDevice, h->stream) != hipSuccess) {
+        (void)hipFree(W);
+        return CAQR_ERR_DEVICE;
+      }
+    }
+    caqr_status_t st = caqr::ls_solve_ws(h, m, n, nrhs, W ? W : A, W ? std::max<int64_t>(m, 1) : lda, B, ldb, nullptr,
+                                         info);
+    if (W) (void)hipFree(W);
+    return st;
+  }
   return caqr::ls_solve_ws(h, m, n, nrhs, A, lda, B, ldb, nullptr, info);
 }
 
@@ -1102,6 +1136,152 @@ size_t ls_workspace_bytes(int64_t m, int64_t n) {
   return factor_ws_bytes(m, n, n <= kNbMax ? std::max<int64_t>(n, 1) : kNbMax, 256, nullptr);
 }
 
+// Mixed-precision least squares (arguments validated, n > 64): the copy W of
+// A factored with FP32 leaf products in the trailing updates, x0 = R~^-1
+// (Q~^T b)(0:n), then per right-hand side CGLS on A R~^-1 in FP64 until the
+// backward-error bound reaches tol (checked on a recomputed residual), or the
+// FP64 solve when it does not (unless no_fallback).
+caqr_status_t ls_solve_mixed(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                             double *B, int64_t ldb, const caqr_ls_opts_t &o, caqr_ls_info_t *info) {
+  if (info) *info = caqr_ls_info_t{CAQR_SUCCESS, 0, 0, 0, 0.0};
+  if (n == 0 || nrhs == 0) return CAQR_SUCCESS;
+  const double tol = o.tol > 0.0 ? o.tol : 1e-12;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 30;
+  DeviceGuard g(h->device);
+  hipStream_t s = h->stream;
+  // workspace: W (m x n) | Bq (m x nrhs) right after it (factored as [A | B], so Bq ends as Q~^T B) |
+  // r, q (m) | x, t, p, sv, u, colsq (n) | X (n x nrhs) | scalars
+  const size_t wn = (size_t)m * n, bq = (size_t)m * nrhs, xs = (size_t)n * nrhs;
+  const size_t doubles = wn + bq + 2 * (size_t)m + 6 * (size_t)n + xs + 16;
+  const size_t bytes = doubles * sizeof(double);
+  if (h->ws_limit && bytes > h->ws_limit) return CAQR_ERR_ALLOC;
+  double *ws = nullptr;
+  if (hipMalloc(&ws, bytes) != hipSuccess) return CAQR_ERR_ALLOC;
+  double *W = ws, *Bq = W + wn, *r = Bq + bq, *q = r + m, *x = q + m, *t = x + n, *p = t + n, *sv = p + n,
+         *u = sv + n, *colsq = u + n, *X = colsq + n, *sc = X + xs;
+  // scalars: sc[0] a_lo, sc[1..3] ||u||^2 ||x||^2 ||b||^2, sc[4] gamma, sc[5] gamma', sc[6] delta, sc[7] eta
+  caqr_status_t st = CAQR_SUCCESS;
+  auto ok = [&](hipError_t e) {
+    if (e != hipSuccess && !st) st = CAQR_ERR_DEVICE;
+    return !st;
+  };
+  ok(hipMemcpy2DAsync(W, m * sizeof(double), A, lda * sizeof(double), m * sizeof(double), n, hipMemcpyDeviceToDevice,
+                      s));
+  ok(hipMemcpy2DAsync(Bq, m * sizeof(double), B, ldb * sizeof(double), m * sizeof(double), nrhs,
+                      hipMemcpyDeviceToDevice, s));
+  if (!st) ok(launch_colsq(A, lda, m, n, colsq, s));
+  if (!st) ok(launch_anorm_lower(colsq, n, sc, s));
+  caqr_factors_t F = nullptr;
+  if (!st) st = factor_impl(h, m, n, kNbMax, W, m, nullptr, &F, false, nullptr, nullptr, true, nrhs);
+  if (!st && forced_fault(h)) st = CAQR_ERR_DEVICE;
+  if (!st) ok(launch_trsm_upper(W, m, n, Bq, m, nrhs, s));
+  if (!st) ok(launch_check_solution(W, m, n, Bq, m, nrhs, h->status_dev, s));
+  int64_t stat[2] = {0, 0};
+  if (!st) ok(hipMemcpyAsync(stat, h->status_dev, sizeof(stat), hipMemcpyDeviceToHost, s));
+  if (!st) ok(hipStreamSynchronize(s));
+  if (F) caqr_factors_destroy(F);
+  caqr_status_t num = CAQR_SUCCESS;
+  if (!st && stat[0] > 0)
+    num = CAQR_ERR_SINGULAR;
+  else if (!st && stat[1])
+    num = CAQR_ERR_NONFINITE;
+  int max_iters = 0;
+  double max_eta = 0.0;
+  bool converged = true;
+  for (int64_t k = 0; k < nrhs && !st && !num; ++k) {
+    const double *bk = B + k * ldb;
+    double *xk = X + k * n;
+    ok(launch_copy(x, Bq + k * m, n, s));
+    ok(launch_dot(bk, bk, m, sc + 3, s));
+    bool restart = true;   // recompute r = b - A x and restart the iteration from it
+    bool measured = false; // the bound below was taken on a recomputed residual
+    int it = 0, stall = 0;
+    double eta = 0.0, best = 1e300;
+    for (;;) {
+      if (restart) {  // r = b - A x, u = A^T r, s = R~^-T u, p = s, gamma = s.s
+        ok(launch_resid(A, lda, m, n, x, bk, r, s));
+        ok(launch_atr(A, lda, m, n, r, u, s));
+        ok(launch_copy(sv, u, n, s));
+        ok(launch_trsv_upper_t(W, m, n, sv, s));
+        ok(launch_copy(p, sv, n, s));
+        ok(launch_dot(sv, sv, n, sc + 4, s));
+        restart = false;
+        measured = true;
+      }
+      ok(launch_dot(u, u, n, sc + 1, s));
+      ok(launch_dot(x, x, n, sc + 2, s));
+      ok(launch_eta_bound(sc + 1, sc, sc + 7, s));
+      ok(hipMemcpyAsync(&eta, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+      ok(hipStreamSynchronize(s));
+      if (st || !(eta == eta)) break;  // device error, or NaN
+      if (eta <= tol) {
+        if (measured) break;  // met on a recomputed residual
+        restart = true;       // confirm it on one
+        continue;
+      }
+      stall = (eta < 0.5 * best) ? 0 : stall + 1;
+      best = std::min(best, eta);
+      if (it >= max_iter || stall >= 4) break;
+      // one CGLS step: t = R~^-1 p, q = A t, alpha = gamma / q.q, x += alpha t,
+      // r -= alpha q, u = A^T r, s = R~^-T u, p = s + (s.s / gamma) p
+      ok(launch_copy(t, p, n, s));
+      ok(launch_trsm_upper(W, m, n, t, n, 1, s));
+      ok(launch_gemv(A, lda, m, n, t, q, s));
+      ok(launch_dot(q, q, m, sc + 6, s));
+      ok(launch_axpy_ratio(x, t, n, sc + 4, sc + 6, 1.0, s));
+      ok(launch_axpy_ratio(r, q, m, sc + 4, sc + 6, -1.0, s));
+      ok(launch_atr(A, lda, m, n, r, u, s));
+      ok(launch_copy(sv, u, n, s));
+      ok(launch_trsv_upper_t(W, m, n, sv, s));
+      ok(launch_dot(sv, sv, n, sc + 5, s));
+      ok(launch_xpby_ratio(p, sv, n, sc + 5, sc + 4, s));
+      ok(launch_copy(sc + 4, sc + 5, 1, s));
+      ++it;
+      measured = false;
+      if (it % 16 == 0) restart = true;  // the recursive residual drifts: recompute it now and then
+    }
+    ok(launch_copy(xk, x, n, s));
+    max_iters = std::max(max_iters, it);
+    max_eta = std::max(max_eta, eta);
+    if (!(eta <= tol)) converged = false;
+  }
+  if (!st && !num && converged) {  // solutions into B(0:n, :)
+    ok(hipMemcpy2DAsync(B, ldb * sizeof(double), X, n * sizeof(double), n * sizeof(double), nrhs,
+                        hipMemcpyDeviceToDevice, s));
+    ok(hipStreamSynchronize(s));
+  }
+  if (!st && !num && !converged && o.no_fallback) {  // the last iterates, flagged
+    ok(hipMemcpy2DAsync(B, ldb * sizeof(double), X, n * sizeof(double), n * sizeof(double), nrhs,
+                        hipMemcpyDeviceToDevice, s));
+    ok(hipStreamSynchronize(s));
+    num = CAQR_ERR_NOT_CONVERGED;
+  }
+  bool fell_back = false;
+  if (!st && !num && !converged) {  // the FP64 solve of a fresh copy of A
+    ok(hipMemcpy2DAsync(W, m * sizeof(double), A, lda * sizeof(double), m * sizeof(double), n,
+                        hipMemcpyDeviceToDevice, s));
+    caqr_ls_info_t inf2{};
+    if (!st) {
+      const caqr_status_t s2 = ls_solve_ws(h, m, n, nrhs, W, m, B, ldb, nullptr, &inf2);
+      if (s2 == CAQR_ERR_SINGULAR || s2 == CAQR_ERR_NONFINITE) num = s2;
+      else if (s2) st = s2;
+    }
+    fell_back = true;
+    if (info) info->index = inf2.index;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(ws);
+  if (st) return st;
+  if (info) {
+    info->status = num;
+    if (num == CAQR_ERR_SINGULAR && !fell_back) info->index = stat[0] - 1;
+    info->iters = max_iters;
+    info->fallback = fell_back ? 1 : 0;
+    info->eta = max_eta;
+  }
+  return num;
+}
+
 caqr_status_t reserve_tickets(caqr_handle_t h, size_t counters) {
   DeviceGuard g(h->device);
   return ensure_tickets(h, counters);
@@ -1118,12 +1298,17 @@ caqr_status_t ls_solve_ws(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, d
   if (n == 0 || nrhs == 0) return CAQR_SUCCESS;
   DeviceGuard g(h->device);
   int64_t *status_dev = status ? status : h->status_dev;
+  // B stored right after A (same leading dimension): B rides along as extra
+  // trailing columns of the factorization and ends as Q^T B, no separate pass
+  const bool aug = B == A + lda * n && ldb == lda && nrhs <= 64;
+  const int64_t extra = aug ? nrhs : 0;
   caqr_factors_t F = nullptr;
   caqr_status_t st =
-      (n <= kNbMax) ? factor_impl(h, m, n, std::max<int64_t>(n, 1), A, lda, nullptr, &F, true, ws, tickets)
-                    : factor_impl(h, m, n, kNbMax, A, lda, nullptr, &F, false, ws, tickets);
+      (n <= kNbMax)
+          ? factor_impl(h, m, n, std::max<int64_t>(n, 1), A, lda, nullptr, &F, true, ws, tickets, false, extra)
+          : factor_impl(h, m, n, kNbMax, A, lda, nullptr, &F, false, ws, tickets, false, extra);
   if (st) return st;
-  st = apply_q(h, F, CAQR_OP_T, nrhs, B, ldb);
+  if (!aug) st = apply_q(h, F, CAQR_OP_T, nrhs, B, ldb);
   if (!st && forced_fault(h)) st = CAQR_ERR_DEVICE;
   if (!st && launch_trsm_upper(A, lda, n, B, ldb, nrhs, h->stream) != hipSuccess) st = CAQR_ERR_DEVICE;
   if (!st && launch_check_solution(A, lda, n, B, ldb, nrhs, status_dev, h->stream) != hipSuccess)

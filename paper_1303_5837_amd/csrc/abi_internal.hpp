@@ -24,6 +24,11 @@ caqr_status_t ls_solve_ws(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, d
                           int64_t ldb, void *ws, caqr_ls_info_t *info, unsigned *tickets = nullptr,
                           int64_t *status = nullptr);
 
+// Mixed-precision least-squares solve (validated arguments, n > 64): A only
+// read; solutions in B(0:n, :).  Allocates its workspace.
+caqr_status_t ls_solve_mixed(caqr_handle_t h, int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                             double *B, int64_t ldb, const caqr_ls_opts_t &o, caqr_ls_info_t *info);
+
 // Pre-size the handle's ticket counters (device-tree synchronization).
 caqr_status_t reserve_tickets(caqr_handle_t h, size_t counters);
 

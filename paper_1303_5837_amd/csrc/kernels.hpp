@@ -49,6 +49,7 @@ struct UpdateParams {
   int tiles;          // column tiles of kUpdTile
   int arity;          // tree arity K: 2 or 4
   int stride;         // node kernels: tree level processed, as its stride s = K^j
+  int f32;            // 1: the leaf products Y^T C and Y W on FP32 MFMA (mixed-precision factorization)
   unsigned *tickets;  // [kTreeTiles * L] zero on entry and exit, or null; with
                       // tickets, a Q^T of at most kTreeTiles tiles runs the
                       // whole tree in one launch

@@ -12,25 +12,31 @@ namespace {
 constexpr int kBlk = 64;  // diagonal block of the blocked back substitution
 
 // One workgroup per right-hand side.  Blocks of 64 rows from the bottom: the
-// 64x64 diagonal block is solved by wave 0 (row-by-row, lane = row), then the
-// rows above are updated by the whole workgroup, B(0:j0) -= R(0:j0, blk) x_blk.
+// 64x64 diagonal block is staged in LDS (coalesced, one round trip) and solved
+// by wave 0 (row by row, lane = row, every R entry an LDS read), then the rows
+// above are updated by the whole workgroup, B(0:j0) -= R(0:j0, blk) x_blk.
 __global__ void __launch_bounds__(kThreads) trsm_upper_kernel(const double *R, int64_t ldr, int64_t n, double *B,
                                                                int64_t ldb) {
   double *b = B + (int64_t)blockIdx.x * ldb;
   __shared__ double xs[kBlk];
+  __shared__ double rd[kBlk][kBlk + 1];  // diagonal block, rd[col][row]
   const int tid = threadIdx.x;
   for (int64_t j1 = n; j1 > 0; j1 -= kBlk) {
     const int64_t j0 = (j1 >= kBlk) ? j1 - kBlk : 0;
     const int nb = (int)(j1 - j0);
+    for (int e = tid; e < kBlk * kBlk; e += kThreads) {
+      const int row = e % kBlk, col = e / kBlk;
+      rd[col][row] = (row < nb && col < nb && row <= col) ? R[(j0 + row) + (j0 + col) * ldr] : 0.0;
+    }
+    __syncthreads();
     if (tid < 64) {
       // lane t owns row j0 + t of the block
       double bt = (tid < nb) ? b[j0 + tid] : 0.0;
       for (int i = nb - 1; i >= 0; --i) {
-        const double rii = R[(j0 + i) + (j0 + i) * ldr];
         const double bi = __shfl(bt, i);
-        const double xi = bi / rii;
+        const double xi = bi / rd[i][i];
         if (tid == i) bt = xi;
-        if (tid < i) bt = fma(-R[(j0 + tid) + (j0 + i) * ldr], xi, bt);
+        if (tid < i) bt = fma(-rd[i][tid], xi, bt);
       }
       if (tid < nb) {
         b[j0 + tid] = bt;
@@ -39,9 +45,14 @@ __global__ void __launch_bounds__(kThreads) trsm_upper_kernel(const double *R, i
     }
     __syncthreads();
     for (int64_t row = tid; row < j0; row += kThreads) {
-      double s = b[row];
-      for (int k = 0; k < nb; ++k) s = fma(-R[row + (j0 + k) * ldr], xs[k], s);
-      b[row] = s;
+      double s0 = b[row], s1 = 0.0;
+      int k = 0;
+      for (; k + 1 < nb; k += 2) {
+        s0 = fma(-R[row + (j0 + k) * ldr], xs[k], s0);
+        s1 = fma(-R[row + (j0 + k + 1) * ldr], xs[k + 1], s1);
+      }
+      if (k < nb) s0 = fma(-R[row + (j0 + k) * ldr], xs[k], s0);
+      b[row] = s0 + s1;
     }
     __syncthreads();
   }

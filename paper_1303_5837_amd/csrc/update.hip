@@ -76,6 +76,19 @@ __device__ __forceinline__ f64x4 *xch_at(double *buf, int rh, int cg, int a, int
 
 __device__ __forceinline__ int pi16(int li) { return 4 * (li & 3) + (li >> 2); }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 MFMA 16x16x4 with FP32 accumulation (the lower-precision trailing
+// update): operands as in the FP64 instruction (A(i, k) in lane i + 16 k,
+// B(k, j) in lane j + 16 k), result D(i, j) in lane j + 16 (i / 4), register
+// i % 4 -- already the contiguous layout, so its A operand is read at row
+// lane % 16 of the slab (no permutation).
+__device__ __forceinline__ f32x4 mfma16x16x4_f32(double a, double b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f64x4 to_f64x4(f32x4 v) { return f64x4{v[0], v[1], v[2], v[3]}; }
+
 __device__ __forceinline__ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
 // C slab load/store (contiguous layout) with row/column masking.
@@ -402,7 +415,10 @@ __device__ __forceinline__ void scale_top_rows_own(const UpdateParams &u, int ti
 // then chunks n-1..0 for C -= Y W'; chunk c sits in buffer c % 2, T in buffer
 // n % 2, and the W partials are exchanged in the last chunk's buffer.
 // Every chunk of C is stored as soon as it is final.
-template <int NQ, int RT, bool TRANS>
+// F32: the two products with Y (W = Y^T C and Y W) on FP32 MFMA, each
+// accumulated in FP32 from zero (operands rounded to FP32); W' = T^T W, the
+// exchange of the partial sums and C itself stay FP64 (C -= the FP32 product).
+template <int NQ, int RT, bool TRANS, bool F32 = false>
 __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int tile, UpdSmem &sm) {
   constexpr int H = 16 * RT;       // leaf rows
   constexpr int HALF = H / 2;      // rows per wave
@@ -413,7 +429,7 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
   const int wave = tid >> 6;
   const int cg = wave & 1, rh = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
-  const int pl = pi16(li);
+  const int pl = F32 ? li : pi16(li);
   const int64_t row0 = (int64_t)leaf * u.h;
   const int64_t col = (int64_t)tile * kUpdTile + 16 * cg + li;
   const bool colok = col < u.k;
@@ -441,8 +457,11 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
 
   // ---- partial W = Y^T C over this wave's rows, chunk by chunk
   f64x4 w[NQ];
+  f32x4 w32[F32 ? NQ : 1];
 #pragma unroll
   for (int a = 0; a < NQ; ++a) w[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < (F32 ? NQ : 1); ++a) w32[a] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < NCHUNK; ++c) {
     if (c + 1 < NCHUNK)
@@ -459,8 +478,13 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
       for (int a = 0; a < NQ; ++a) {
         if (xl < a) continue;  // rows above block a are zero
         const f64x4 y = lds_col4(ys, 16 * a + pl, 32 * rh + 16 * tt + 4 * lk);
+        if constexpr (F32) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(y[r], acc[x][r], w[a]);
+          for (int r = 0; r < 4; ++r) w32[F32 ? a : 0] = mfma16x16x4_f32(y[r], acc[x][r], w32[F32 ? a : 0]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(y[r], acc[x][r], w[a]);
+        }
       }
     }
     if (c + 1 < NCHUNK && 32 * (c + 1) < kMaxB)  // rows of the leaf's top triangle
@@ -473,6 +497,10 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
   // loaded again meanwhile for the second pass.
   stage_load_split<kLeafY>(st, u.Y, u.ldy, row0 + 32 * (NCHUNK - 1), row0 + HALF + 32 * (NCHUNK - 1),
                            32 * (NCHUNK - 1), HALF + 32 * (NCHUNK - 1), u.m, u.b, vec_y, tid);
+  if constexpr (F32) {
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) w[a] = to_f64x4(w32[F32 ? a : 0]);
+  }
   exchange_w<NQ>(w, sm.buf[(NCHUNK - 1) & 1]);
   apply_t_lds<NQ, TRANS>(sm.buf[NCHUNK & 1], w);
 #pragma unroll
@@ -496,6 +524,7 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
                                  HALF + 32 * (c - 2), u.m, u.b, vec_y, tid);
     }
     const double *ys = sm.buf[c & 1];
+    f32x4 prod[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};  // FP32: Y W of this chunk
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
       const int x = 2 * c + tt;
@@ -504,9 +533,18 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
       for (int a = 0; a < NQ; ++a) {
         if (xl < a) continue;
         const f64x4 y = lds_row4(ys, 32 * rh + 16 * tt + pl, 16 * a + 4 * lk);
+        if constexpr (F32) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(y[r], w[a][r], acc[x]);
+          for (int r = 0; r < 4; ++r) prod[tt] = mfma16x16x4_f32(y[r], w[a][r], prod[tt]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(y[r], w[a][r], acc[x]);
+        }
       }
+    }
+    if constexpr (F32) {
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) acc[2 * c + tt] += to_f64x4(prod[tt]);
     }
     // rows of chunk c are final
 #pragma unroll
@@ -524,12 +562,12 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
 
 // Leaf updates of one panel, one workgroup per (leaf, tile): Q^T (TRANS) runs
 // them before the tree levels, Q after them.  No workgroup depends on another.
-template <int NQ, int RT, bool TRANS>
+template <int NQ, int RT, bool TRANS, bool F32 = false>
 __global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
   const int leaf = blockIdx.x % u.L;
   const int tile = blockIdx.x / u.L;
-  leaf_update<NQ, RT, TRANS>(u, leaf, tile, sm);
+  leaf_update<NQ, RT, TRANS, F32>(u, leaf, tile, sm);
 }
 
 // Q^T leaf updates of the K neighbouring leaves of one first-level group
@@ -537,7 +575,7 @@ __global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
 // just written by this workgroup, so no other workgroup is involved): one
 // workgroup per (group, tile), and the level launches start at the second
 // level.
-template <int NQ, int RT, int K>
+template <int NQ, int RT, int K, bool F32 = false>
 __global__ void __launch_bounds__(kUThreads, 2) leaf_group_kernel(UpdateParams u) {
   static_assert(K == 2, "wider nodes are applied by their own level launches");
   __shared__ UpdSmem sm;
@@ -547,10 +585,10 @@ __global__ void __launch_bounds__(kUThreads, 2) leaf_group_kernel(UpdateParams u
   const int g = K * gi;
   const int cnt = min(K, u.L - g);
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
-  leaf_update<NQ, RT, true>(u, g, tile, sm);  // each ends with a barrier: the leaf's C stored
+  leaf_update<NQ, RT, true, F32>(u, g, tile, sm);  // each ends with a barrier: the leaf's C stored
   if constexpr (K == 2) {
     if (g + 1 < u.L) {
-      leaf_update<NQ, RT, true>(u, g + 1, tile, sm);
+      leaf_update<NQ, RT, true, F32>(u, g + 1, tile, sm);
       node_update<NQ, true>(u, g, g + 1, tile, sm, vec_ok);
     }
   }
@@ -600,7 +638,7 @@ __device__ __forceinline__ bool arrive(unsigned *tickets, int node, int cnt, int
 // node's update, the others exit.  The grouping is fixed by index, so the
 // result does not depend on arrival order.  The workgroup that completes the
 // root applies D.
-template <int NQ, int RT, int K>
+template <int NQ, int RT, int K, bool F32 = false>
 __global__ void __launch_bounds__(kUThreads, node_wgs_per_cu<K>()) qt_tree_tile_kernel(UpdateParams u) {
   __shared__ typename NodeSmem<K>::type sm;
   __shared__ int flag;
@@ -608,7 +646,7 @@ __global__ void __launch_bounds__(kUThreads, node_wgs_per_cu<K>()) qt_tree_tile_
   const int leaf = blockIdx.x % u.L;
   const int tile = blockIdx.x / u.L;
   unsigned *tickets = u.tickets + (int64_t)tile * u.L;  // each tile climbs its own tree
-  leaf_update<NQ, RT, true>(u, leaf, tile, leaf_smem<K>(sm));
+  leaf_update<NQ, RT, true, F32>(u, leaf, tile, leaf_smem<K>(sm));
   int rt = leaf;  // root of the subtree this workgroup holds
   for (int s = 1; s < u.L; s *= K) {
     const int g = rt - rt % (K * s);  // survivor of rt's group at this level
@@ -621,10 +659,10 @@ __global__ void __launch_bounds__(kUThreads, node_wgs_per_cu<K>()) qt_tree_tile_
   scale_top_rows_own<NQ>(u, tile);
 }
 
-template <int NQ, int RT, int K>
+template <int NQ, int RT, int K, bool F32>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   if (u.tickets && u.tiles <= kTreeTiles && u.L > 1) {
-    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT, K>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
+    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT, K, F32>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
     return hipGetLastError();
   }
   // binary trees: leaf pairs with the first level, then the tree bottom-up (one
@@ -633,10 +671,11 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   // reaches free CUs sooner), then every level by its own launch.
   int st0 = 1;
   if constexpr (K == 2) {
-    hipLaunchKernelGGL((leaf_group_kernel<NQ, RT, K>), dim3((u.L + K - 1) / K * u.tiles), dim3(kUThreads), 0, s, u);
+    hipLaunchKernelGGL((leaf_group_kernel<NQ, RT, K, F32>), dim3((u.L + K - 1) / K * u.tiles), dim3(kUThreads), 0,
+                       s, u);
     st0 = K;
   } else {
-    hipLaunchKernelGGL((leaf_kernel<NQ, RT, true>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
+    hipLaunchKernelGGL((leaf_kernel<NQ, RT, true, F32>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
   }
   for (int st = st0; st < u.L; st *= K) {
     UpdateParams v = u;
@@ -663,13 +702,18 @@ hipError_t launch_qn_t(const UpdateParams &u, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NQ, int RT, int K>
+hipError_t launch_qt_p(const UpdateParams &u, hipStream_t s) {
+  return u.f32 ? launch_qt_t<NQ, RT, K, true>(u, s) : launch_qt_t<NQ, RT, K, false>(u, s);
+}
+
 template <int RT, int K>
 hipError_t dispatch_nq(const UpdateParams &u, bool trans, hipStream_t s) {
   switch ((u.b + 15) / 16) {
-    case 1: return trans ? launch_qt_t<1, RT, K>(u, s) : launch_qn_t<1, RT, K>(u, s);
-    case 2: return trans ? launch_qt_t<2, RT, K>(u, s) : launch_qn_t<2, RT, K>(u, s);
-    case 3: return trans ? launch_qt_t<3, RT, K>(u, s) : launch_qn_t<3, RT, K>(u, s);
-    case 4: return trans ? launch_qt_t<4, RT, K>(u, s) : launch_qn_t<4, RT, K>(u, s);
+    case 1: return trans ? launch_qt_p<1, RT, K>(u, s) : launch_qn_t<1, RT, K>(u, s);
+    case 2: return trans ? launch_qt_p<2, RT, K>(u, s) : launch_qn_t<2, RT, K>(u, s);
+    case 3: return trans ? launch_qt_p<3, RT, K>(u, s) : launch_qn_t<3, RT, K>(u, s);
+    case 4: return trans ? launch_qt_p<4, RT, K>(u, s) : launch_qn_t<4, RT, K>(u, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -686,6 +730,7 @@ hipError_t dispatch_k(const UpdateParams &u, bool trans, hipStream_t s) {
 
 hipError_t dispatch(const UpdateParams &u, bool trans, hipStream_t s) {
   if (u.b < 1 || u.b > kMaxB || u.L < 1 || u.k < 1 || u.m < 1) return hipErrorInvalidValue;
+  if (u.f32 && !trans) return hipErrorInvalidValue;  // the FP32 products serve the factorization's Q^T only
   if (u.arity == 2) return dispatch_k<2>(u, trans, s);
   if (u.arity == 4) return dispatch_k<4>(u, trans, s);
   return hipErrorInvalidValue;

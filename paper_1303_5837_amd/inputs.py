@@ -97,3 +97,15 @@ def conditioned_device(m: int, n: int, kappa: float, seed: int, device="cuda"):
     A = torch.empty((n, m), dtype=torch.float64, device=device).t()
     torch.matmul(G, W, out=A)
     return A
+
+
+def conditioned_host(m: int, n: int, kappa: float, seed: int) -> np.ndarray:
+    """A = U diag(s) V^T on the host, column-major: U the orthonormal factor of
+    an m-by-n N(0,1) draw and V of an n-by-n one (host LAPACK QR, input
+    construction only), s geometric from 1 to 1/kappa, so ||A||_2 = 1 and
+    kappa(A) = kappa (the mixed-precision least-squares configuration)."""
+    rngs = substreams(seed, 2)
+    U = np.linalg.qr(rngs[0].standard_normal((m, n)))[0]
+    V = np.linalg.qr(rngs[1].standard_normal((n, n)))[0]
+    s = geometric_singular_values(n, kappa)
+    return np.asfortranarray((U * s) @ V.T)

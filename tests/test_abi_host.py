@@ -235,3 +235,18 @@ def test_arity_validation_without_device():
                                    ctypes.byref(f)) == 1  # valid arity-4 plan: the NULL handle fails
     assert lib.tsqr_factor_batched(None, 1, M, N, P, M, caqr.F64, ctypes.byref(caqr.TreeOpts(0, 2, 0, 4)),
                                    ctypes.byref(f)) == 1  # two leaves per workgroup with arity 4: invalid
+
+
+def test_ls_options_validation_without_device():
+    """caqr_ls_opts_t: precision 0 or 1, max_iter >= 0, tol >= 0, no_fallback 0
+    or 1, reserved 0 (checked before the sizes' NOT_SUPPORTED, so an m < n call
+    separates a bad option, 1, from a good one, 4)."""
+    lib = caqr.library()
+    A = ctypes.c_void_p(0x1000)
+    good = [caqr.LsOpts(0, 0, 0.0, 0, 0), caqr.LsOpts(1, 0, 0.0, 0, 0), caqr.LsOpts(1, 50, 1e-10, 1, 0)]
+    bad = [caqr.LsOpts(2, 0, 0.0, 0, 0), caqr.LsOpts(1, -1, 0.0, 0, 0), caqr.LsOpts(1, 0, -1e-12, 0, 0),
+           caqr.LsOpts(1, 0, float("nan"), 0, 0), caqr.LsOpts(1, 0, 0.0, 2, 0), caqr.LsOpts(1, 0, 0.0, 0, 3)]
+    for o in good:
+        assert lib.ls_solve(None, 5, 6, 1, A, 5, A, 5, ctypes.byref(o), None) == 4
+    for o in bad:
+        assert lib.ls_solve(None, 5, 6, 1, A, 5, A, 5, ctypes.byref(o), None) == 1
