@@ -2,15 +2,16 @@
 """Benchmark of the multilevel QR path on one MI355X.
 
 Headline: CAQR FP64 GFLOP/s on an 8192 x 8192 N(0,1) matrix (seed 2), panel
-width 64, leaf rows 256, binary tree per panel (one 256-row leaf per
+width 64, leaf rows 256, arity-4 tree per panel (one 256-row leaf per
 workgroup, then the device-wide levels), flops counted as LAPACK's 4 n^3 / 3.  One step = one factorization
 (every panel: leaf QR, reduction tree, trailing update).  A is restored from a
 pristine device copy before each step, outside the event-timed factorization.
 
-Also reported: the live roofline of the dominant kernel (the trailing update on
-FP64 MFMA, from HIP events the library records around each launch on its
-stream), the oracle's CPU rate on a bounded sample, and TSQR on 1,048,576 x 64
-and 4096 x 32 as secondary lines.
+Also reported: the live rooflines of the panel kernel and of the trailing
+update (from HIP events the library records around each launch on the stream
+it runs on), the dominant one as `roofline`; the oracle's CPU rate on the
+headline workload; and secondary lines (TSQR, batched, least squares, mixed
+precision, served stream).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -38,29 +39,55 @@ def update_flops(rows: int, cols: int, b: int, leaves: int) -> float:
 
 
 UPDATE_SOURCES = ("update.hip", "staging.hpp", "kernels.hpp", "device_common.hpp")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "caqr_8192_update_traffic.md")
+PANEL_SOURCES = ("panel_body.hpp", "panel_a4.hip", "kernels.hpp", "device_common.hpp")
+TRAFFIC_PROFILES = {
+    "update": (os.path.join(ROOT, "profiles", "caqr_8192_update_traffic.md"), UPDATE_SOURCES),
+    "panel": (os.path.join(ROOT, "profiles", "caqr_8192_panel_traffic.md"), PANEL_SOURCES),
+}
 
 
-def update_traffic_per_call():
-    """Measured HBM bytes per trailing-update call (rocprofv3 FETCH_SIZE and
-    WRITE_SIZE, scaled by the same counters on a plain copy), from the committed
-    profile summary; None when the update's sources changed since it was taken."""
+def traffic_per_call(which):
+    """Measured HBM bytes per call of a kernel (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, scaled by the same counters on a plain copy), from the
+    committed profile summary; None when the kernel's sources changed since it
+    was taken (their hash is recorded with the figure)."""
     import hashlib
     import re
 
+    path, sources = TRAFFIC_PROFILES[which]
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None
-    m_b = re.search(r"update_traffic_bytes_per_call: (\d+)", text)
-    m_h = re.search(r"update_sources_sha256: ([0-9a-f]+)", text)
+    m_b = re.search(r"traffic_bytes_per_call: (\d+)", text)
+    m_h = re.search(r"sources_sha256: ([0-9a-f]+)", text)
     if not (m_b and m_h):
         return None
     h = hashlib.sha256()
-    for f in UPDATE_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1303_5837_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return int(m_b.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
+def sources_sha256(which):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC_PROFILES[which][1]:
+        with open(os.path.join(ROOT, "paper_1303_5837_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def panel_flops(rows, b, h=256):
+    """Flops of one panel factorization (leaf QRs and stacked eliminations)."""
+    L = -(-rows // h)
+    total = 0.0
+    for i in range(L):
+        hi = max(min(h, rows - i * h), b)
+        total += 2.0 * hi * b * b - 2.0 * b ** 3 / 3.0
+    return total + (L - 1) * 2.0 * b ** 3 / 3.0
 
 
 def executed_flops(m: int, n: int, nb: int, h: int = 256) -> float:
@@ -539,10 +566,11 @@ def main():
         F.close()
     torch.cuda.synchronize()
 
-    # events bracket only the trailing-update calls run as a leaf launch plus
-    # one launch per tree level (the roofline's kernel, off the panel chain);
-    # events on the chain itself would lengthen the step they measure
-    h.set_trace_kinds(["update_t_levels"])
+    # events bracket the panel factorizations (leaf QRs and the tree climb, one
+    # launch each, on the handle's stream) and the wide trailing-update calls
+    # (a leaf launch plus one launch per tree level, on the second stream):
+    # the two kernels whose rooflines the line reports
+    h.set_trace_kinds(["panel", "update_t_levels"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     events = []
@@ -559,11 +587,67 @@ def main():
     lapack_flops = 4.0 * n ** 3 / 3.0
     gflops = lapack_flops / (ms * 1e-3) / 1e9
 
+    # diagnostics outside the timed steps: the step without any event, and one
+    # step with every launch bracketed (the panel chain's parts)
+    untraced = []
+    for _ in range(2):
+        F, e0, e1 = one_step()
+        F.close()
+        untraced.append(e0.elapsed_time(e1))
+    h.set_trace(True)
+    F, e0, e1 = one_step()
+    F.close()
+    full = h.take_trace()
+    h.set_trace(False)
+    chain = {}
+    for e in full:
+        chain[e["kind"]] = chain.get(e["kind"], 0.0) + e["ms"]
+
     upd = [e for e in trace if e["kind"] == "update_t_levels"]
     upd_alg_bytes = sum(16.0 * e["rows"] * e["cols"] for e in upd) / max(1, len(upd))
     upd_ms = sum(e["ms"] for e in upd)
     upd_flops = sum(update_flops(e["rows"], e["cols"], e["width"], e["leaves"]) for e in upd)
-    achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    upd_achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    pan = [e for e in trace if e["kind"] == "panel"]
+    pan_bytes = sum(panel_bytes(e["rows"], e["width"]) for e in pan)
+    pan_ms = sum(e["ms"] for e in pan)
+    pan_gbs = pan_bytes / (pan_ms * 1e-3) / 1e9 if pan_ms > 0 else 0.0
+    pan_tflops = sum(panel_flops(e["rows"], e["width"]) for e in pan) / (pan_ms * 1e-3) / 1e12 if pan_ms > 0 else 0.0
+    roof_update = {
+        "kernel": "trailing update call Q_s^T C of the columns beyond the next panel: leaf_kernel (one "
+                  "workgroup per leaf and 32-column tile) + one node_level_kernel per tree level + "
+                  "scale_rows_kernel",
+        "bound": "mfma",
+        "achieved": round(upd_achieved, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(upd_achieved / PEAK_FP64_TFLOPS, 4),
+        "traffic": traffic_per_call("update"),
+        "traffic_unit": "HBM bytes per update call (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "traffic_algorithmic": round(upd_alg_bytes),
+        "launches_per_step": len(upd) // max(1, args.steps),
+        "avg_launch_ms": round(upd_ms / max(1, len(upd)), 5),
+        "share_of_step": round(upd_ms / max(1e-9, sum(step_ms)), 4),
+    }
+    roof_panel = {
+        "kernel": "panel factorization tsqr_panel_kernel (256-row leaves, one per workgroup, and the arity-4 "
+                  "tree climbed with tickets): one launch per panel",
+        "bound": "hbm",
+        "achieved": round(pan_gbs, 3),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(pan_gbs / PEAK_HBM_GBS, 5),
+        "traffic": traffic_per_call("panel"),
+        "traffic_unit": "HBM bytes per panel launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "traffic_algorithmic": round(pan_bytes / max(1, len(pan))),
+        "algorithmic_bytes": "16 m_s b per panel (read the panel, write its Y and R)",
+        "fp64_tflops": round(pan_tflops, 4),
+        "launches_per_step": len(pan) // max(1, args.steps),
+        "avg_launch_ms": round(pan_ms / max(1, len(pan)), 5),
+        "share_of_step": round(pan_ms / max(1e-9, sum(step_ms)), 4),
+        "bound_note": "latency: 64 sequential Householder steps per leaf and per tree level",
+    }
+    panel_dominant = pan_ms >= upd_ms
 
     out = {
         "metric": "CAQR FP64 GFLOP/s (% peak); batched LS solves/s + p99 latency vs plain",
@@ -579,7 +663,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"caqr_fp64_{n}x{n}_nb{nb}", "m": n, "n": n, "nb": nb, "leaf_rows": 256,
-                   "tree": "binary per panel: 256-row leaf per workgroup (leaves_per_wg 1), device-wide levels", "seed": inputs.SEEDS["caqr_8192sq"],
+                   "tree": "arity 4 per panel: 256-row leaf per workgroup (leaves_per_wg 1), device-wide levels "
+                           "by tickets", "seed": inputs.SEEDS["caqr_8192sq"],
                    "flop_count": "LAPACK 4n^3/3"},
         "pct_fp64_peak": round(100.0 * gflops / (PEAK_FP64_TFLOPS * 1e3), 2),
         "gflops_executed": round(executed_flops(n, n, nb) / (ms * 1e-3) / 1e9, 2),
@@ -587,22 +672,13 @@ def main():
         "step_ms": [round(x, 4) for x in step_ms],
         "step_ms_p10_p50_p90": [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],
         "wall_ms_timed_region": round(wall_ms, 2),
-        "roofline": {
-            "kernel": "trailing update call Q_s^T C run as leaf_pair_kernel (leaf pairs and the first tree "
-                      "level) + one node_level_kernel per further level + scale_rows_kernel (the columns beyond "
-                      "the next panel)",
-            "bound": "mfma",
-            "achieved": round(achieved, 3),
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-            "traffic": update_traffic_per_call(),
-            "traffic_unit": "HBM bytes per update call (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "traffic_algorithmic": round(upd_alg_bytes),
-            "launches_per_step": len(upd) // max(1, args.steps),
-            "avg_launch_ms": round(upd_ms / max(1, len(upd)), 5),
-            "update_share_of_step": round(upd_ms / max(1e-9, sum(step_ms)), 4),
-        },
+        "ms_per_step_untraced": round(float(np.mean(untraced)), 4),
+        "panel_chain_ms_per_step": {k: round(v, 3) for k, v in sorted(chain.items())},
+        "panel_chain_note": "one step with every launch bracketed: panel = panel kernels, form_t = T "
+                            "formation, update_t = the next panel's single-launch update (these three are the "
+                            "chain), update_t_levels = the wide updates beside it",
+        "roofline": roof_panel if panel_dominant else roof_update,
+        "roofline_other": roof_update if panel_dominant else roof_panel,
     }
     del F
     A0 = A = None

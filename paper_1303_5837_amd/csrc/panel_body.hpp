@@ -569,6 +569,22 @@ __device__ __forceinline__ bool arrive_k(const PanelParamsT<T> &p, int node, int
 // Members present in the group of survivor g at stride s (slots g + t s < L).
 __device__ __forceinline__ int group_count(int g, int s, int K, int L) { return min(K, (L - g + s - 1) / s); }
 
+// combine_k for a node of a K-ary tree with cnt members: a node of two
+// members (the last of a level) takes the two-triangle stack, whose steps
+// touch half the chunks of the zero-filled K-member one; the node it writes
+// (R, V over the one eliminated slot, tau at g + s) is the same.
+template <class T, int W, int NCH, int NB, int NS, int K, int IBS = 0, class IB = InnerBlock<T, 0, 1>>
+__device__ __forceinline__ void combine_node(T (&a)[NCH][NS], const PanelParamsT<T> &p, int g, int s, int cnt, int h,
+                                             PanelSmem<T> &sm, IB *ib = nullptr) {
+  if constexpr (K > 2) {
+    if (cnt == 2) {
+      combine_k<T, W, NCH, NB, NS, 2, IBS>(a, p, g, s, cnt, h, sm, ib);
+      return;
+    }
+  }
+  combine_k<T, W, NCH, NB, NS, K, IBS>(a, p, g, s, cnt, h, sm, ib);
+}
+
 
 // Root of the tree: make the diagonal non-negative, R <- D R, record D.
 template <class T, int W, int NCH, int NB, int NS>
@@ -686,7 +702,7 @@ __device__ __forceinline__ void panel_body(const PanelParamsT<T> p, int leaf0) {
       } else if (!DEVICE_TREE || !arrive_k(p, g + s, cnt, sm)) {
         return;  // another workgroup (or a level launch) finishes the node
       }
-      combine_k<T, W, NCH, NB, NS, K, IBS>(a, p, g, s, cnt, H, sm, &ib);
+      combine_node<T, W, NCH, NB, NS, K, IBS>(a, p, g, s, cnt, H, sm, &ib);
       rt = g;
     }
     if (!go_on) continue;
@@ -711,7 +727,7 @@ __global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_level_kernel(PanelPa
   const int g = K * s * (int)blockIdx.x;
   const int cnt = group_count(g, s, K, p.L);
   if (cnt < 2) return;  // the launch covers only groups with two or more members
-  combine_k<double, kPanelWaves, K * NB, NB, NS, K, IBS>(a, p, g, s, cnt, h, sm, &ib);
+  combine_node<double, kPanelWaves, K * NB, NB, NS, K, IBS>(a, p, g, s, cnt, h, sm, &ib);
   if (K * s >= p.L) finish_root<double, kPanelWaves, K * NB, NB, NS>(a, p, sm);
 }
 
@@ -743,8 +759,8 @@ __global__ void __launch_bounds__(64 * kPanelWaves, 2) tsqr_tree_level_kernel(co
   const PanelParamsT<T> p = probs[__builtin_amdgcn_readfirstlane(nd.x)];
   const int w = __builtin_amdgcn_readfirstlane(nd.w);
   T a[K * NB][NS];
-  combine_k<T, kPanelWaves, K * NB, NB, NS, K>(a, p, __builtin_amdgcn_readfirstlane(nd.y),
-                                               __builtin_amdgcn_readfirstlane(nd.z), w >> 16, w & 0xFFF, sm);
+  combine_node<T, kPanelWaves, K * NB, NB, NS, K>(a, p, __builtin_amdgcn_readfirstlane(nd.y),
+                                                  __builtin_amdgcn_readfirstlane(nd.z), w >> 16, w & 0xFFF, sm);
   if ((w >> 12) & 1) finish_root<T, kPanelWaves, K * NB, NB, NS>(a, p, sm);
 }
 
