@@ -478,13 +478,13 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
 // factorization that may use the handle's stream only) each panel's update
 // covers the whole trailing matrix and the next panel follows it.  With more
 // than one panel the loop looks
-// ahead: the next panel's columns are updated first, then the next panel is
-// factored on the handle's stream while the rest of the trailing matrix is
-// updated on a second stream; the next panel's own update waits for that.
-// The panel goes right behind the narrow update in its stream, so its few
-// workgroups are dispatched before the wide update fills the device.  Every
-// launch is ordered by stream order or by an event, and all work ends on the
-// handle's stream.
+// ahead: the next panel's columns are updated on the handle's stream and the
+// next panel is factored right behind them, while the rest of the trailing
+// matrix is updated on a second stream, started as soon as the panel's T is
+// formed (beside the narrow update: the wide update is the longer branch for
+// the wide early panels, so it goes first); the next panel's own update waits
+// for it.  Every launch is ordered by stream order or by an event, and all
+// work ends on the handle's stream.
 caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) {
   caqr_status_t st = CAQR_SUCCESS;
   if (!F->tickets && (st = ensure_tickets(h, factor_tickets(F)))) return st;
@@ -503,10 +503,12 @@ caqr_status_t run_factorization(caqr_handle_t h, caqr_factors_t F, bool form_t) 
       continue;
     }
     const int64_t kn = F->panels[idx + 1].b;  // columns of the next panel (never the extra columns)
-    if ((st = launch_trailing(h, F, idx, c0, kn, h->stream))) return st;
     const bool wide = k > kn;
+    // the wide update needs this panel's Y and T only: it may start beside the
+    // narrow one
+    if (wide && hipEventRecord(h->sync_ev[0], h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
+    if ((st = launch_trailing(h, F, idx, c0, kn, h->stream))) return st;
     if (wide) {
-      if (hipEventRecord(h->sync_ev[0], h->stream) != hipSuccess) return CAQR_ERR_DEVICE;
       if (hipStreamWaitEvent(h->side, h->sync_ev[0], 0) != hipSuccess) return CAQR_ERR_DEVICE;
       if ((st = launch_trailing(h, F, idx, c0 + kn, k - kn, h->side))) return st;
       if (hipEventRecord(h->sync_ev[1], h->side) != hipSuccess) return CAQR_ERR_DEVICE;

@@ -560,13 +560,26 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
   __syncthreads();  // LDS free for the next update
 }
 
+// Workgroups go to the device's eight XCDs round-robin by index, and each XCD
+// has its own L2.  This renumbering gives every XCD one contiguous range of
+// logical indices (a bijection on [0, n) for any n), so that, with the tile
+// index fastest, the workgroups on one XCD share the reflectors and T of few
+// leaves or nodes instead of each XCD fetching all of them.
+__device__ __forceinline__ int xcd_range_index(int bid, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd;
+  const int x = bid % kXcd;
+  return x * q + min(x, r) + bid / kXcd;
+}
+
 // Leaf updates of one panel, one workgroup per (leaf, tile): Q^T (TRANS) runs
 // them before the tree levels, Q after them.  No workgroup depends on another.
 template <int NQ, int RT, bool TRANS, bool F32 = false>
 __global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
   __shared__ UpdSmem sm;
-  const int leaf = blockIdx.x % u.L;
-  const int tile = blockIdx.x / u.L;
+  const int id = xcd_range_index(blockIdx.x, gridDim.x);
+  const int leaf = id / u.tiles;
+  const int tile = id % u.tiles;
   leaf_update<NQ, RT, TRANS, F32>(u, leaf, tile, sm);
 }
 
@@ -579,9 +592,9 @@ template <int NQ, int RT, int K, bool F32 = false>
 __global__ void __launch_bounds__(kUThreads, 2) leaf_group_kernel(UpdateParams u) {
   static_assert(K == 2, "wider nodes are applied by their own level launches");
   __shared__ UpdSmem sm;
-  const int ngroups = (u.L + K - 1) / K;
-  const int gi = blockIdx.x % ngroups;
-  const int tile = blockIdx.x / ngroups;
+  const int id = xcd_range_index(blockIdx.x, gridDim.x);
+  const int gi = id / u.tiles;
+  const int tile = id % u.tiles;
   const int g = K * gi;
   const int cnt = min(K, u.L - g);
   const bool vec_ok = aligned16(u.C) && (u.ldc % 2 == 0) && aligned16(u.Y) && (u.ldy % 2 == 0);
@@ -600,9 +613,9 @@ template <int NQ, bool TRANS, int K>
 __global__ void __launch_bounds__(kUThreads, node_wgs_per_cu<K>()) node_level_kernel(UpdateParams u) {
   __shared__ typename NodeSmem<K>::type sm;
   const int s = u.stride;
-  const int per = (u.L - s + K * s - 1) / (K * s);
-  const int gi = blockIdx.x % per;
-  const int tile = blockIdx.x / per;
+  const int id = xcd_range_index(blockIdx.x, gridDim.x);
+  const int gi = id / u.tiles;
+  const int tile = id % u.tiles;
   const int g = K * s * gi;
   const int cnt = group_members(g, s, K, u.L);
   if (cnt < 2) return;
