@@ -367,13 +367,24 @@ __device__ __forceinline__ void diag_block_steps(T (&a)[NCH][NS], int b, PanelSm
           scal = rcp_nr(alpha_s - beta_s);
           beta = ldexp(beta_s, -sh);
         }
+        // v = x / (alpha - beta) below the diagonal, x taken scaled by 2^sh.
+        // sh is the same in the 16 active lanes (this column's row), so the
+        // branch is uniform: the scaling is done in place first, and only on
+        // the rescue path.
+        if (__builtin_amdgcn_readfirstlane(sh) != 0) {
+#pragma unroll
+          for (int i = 0; i < NACT; ++i) {
+            const bool act = chunk_act<STACK, NB, NACT>(i, D, cnt);
+            if (act && (i > D || r > jj)) a[i][S] = ldexp(a[i][S], sh);
+          }
+        }
 #pragma unroll
         for (int i = 0; i < NACT; ++i) {
           const bool act = chunk_act<STACK, NB, NACT>(i, D, cnt);
           if (!act) continue;
           T vv;
           if (i > D || r > jj) {
-            vv = (sh == 0 ? a[i][S] : ldexp(a[i][S], sh)) * scal;
+            vv = a[i][S] * scal;
             a[i][S] = vv;
           } else if (r == jj && i == D) {
             vv = T(1);

@@ -20,7 +20,11 @@
 // order.  Two workgroups share each CU (registers and LDS are sized for it),
 // so one issues MFMAs while the other waits for memory or a barrier.  The reflectors are staged through LDS in 64x64 blocks
 // (32 rows of each half, double-buffered, loaded with coalesced 16-byte
-// accesses), and T goes through the same buffers.  The tree levels run one
+// accesses), and T goes through the same buffers.  The leaf pass of a wide
+// Q^T update (256-row leaves, b = 64) instead keeps a whole leaf's Y and T in
+// LDS and gives each of eight waves all 256 rows of 16 columns, one
+// workgroup per CU running through many tiles of the same leaf
+// (leaf_res_kernel; the same products in the same order).  The tree levels run one
 // launch per level (nodes of a level and tiles in parallel), so no workgroup
 // ever waits for another; only the single-tile update of the next panel's
 // columns climbs the tree inside one launch, with tickets.
@@ -30,6 +34,8 @@
 // MFMA result layout holds row 4r + lane/16 in register r, so every product
 // whose output uses the contiguous layout reads its A operand at the permuted
 // row pi(lane%16) = 4*(lane%4) + (lane%16)/4 of the slab.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "staging.hpp"
@@ -89,7 +95,7 @@ __device__ __forceinline__ f32x4 mfma16x16x4_f32(double a, double b, f32x4 c) {
 
 __device__ __forceinline__ f64x4 to_f64x4(f32x4 v) { return f64x4{v[0], v[1], v[2], v[3]}; }
 
-__device__ __forceinline__ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+__host__ __device__ __forceinline__ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
 // C slab load/store (contiguous layout) with row/column masking.
 __device__ __forceinline__ f64x4 load_slab(const double *C, int64_t ldc, int64_t grow, int64_t col, int64_t m,
@@ -583,6 +589,218 @@ __global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
   leaf_update<NQ, RT, TRANS, F32>(u, leaf, tile, sm);
 }
 
+// ---- Q^T leaf updates with the leaf's reflectors resident in LDS (256-row
+// leaves, b = 64, FP64): the pass over the leaves of the wide trailing update.
+// A workgroup of eight waves (two per SIMD, one workgroup per CU) keeps Y and
+// T of one leaf in LDS and takes a contiguous run of jobs (leaf, 128-column
+// tile) in leaf-major order, so Y and T are staged once per leaf it visits.
+// Wave w holds columns 16w..16w+15 of the tile over all 256 rows (16 slabs in
+// the contiguous layout): W = Y^T C needs no exchange between waves, and no
+// barrier separates the waves within a job.  Each slab of C is stored as soon
+// as it is final and the next job's slab is loaded into its registers, so
+// the next job's C is in flight during this job's update.  The products are
+// formed in the order of leaf_update (partial sums of rows 0..127 and
+// 128..255 added, T applied, then C += Y W' slab by slab), so the result is
+// bitwise that of leaf_kernel.
+constexpr int kResThreads = 512;
+constexpr int kResCols = 16 * (kResThreads / 64);  // columns of a job
+constexpr int kResRows = 256;                      // leaf rows
+
+// LDS of a workgroup: Y column-major with leading dimension kResLd (the
+// 16 columns, or 16 rows, of one MFMA operand read fall in different banks),
+// and the ten 16x16 blocks of T on and above the diagonal, each column-major
+// with leading dimension 18 (the same property); 151.5 KiB.
+constexpr int kResLd = kResRows + 2;
+constexpr int kTBlk = 16 * 18;
+
+struct ResSmem {
+  alignas(16) double y[kMaxB * kResLd];
+  alignas(16) double t[10 * kTBlk];
+};
+
+__device__ __forceinline__ int t_block(int a, int ao) { return (ao * (ao + 1) / 2 + a) * kTBlk; }
+
+// Rows row0..row0+3 of column col of Y (row0 even).
+__device__ __forceinline__ f64x4 res_col4(const double *y, int col, int row0) {
+  const double *p = y + col * kResLd + row0;
+  const f64x2 lo = *reinterpret_cast<const f64x2 *>(p);
+  const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 2);
+  return f64x4{lo.x, lo.y, hi.x, hi.y};
+}
+
+// Columns col0..col0+3 of row `row` of Y.
+__device__ __forceinline__ f64x4 res_row4(const double *y, int row, int col0) {
+  const double *p = y + col0 * kResLd + row;
+  return f64x4{p[0], p[kResLd], p[2 * kResLd], p[3 * kResLd]};
+}
+
+// Rows 16a + lr0 .. +3 of column 16ao + lc of T (a <= ao; lr0 even).
+__device__ __forceinline__ f64x4 res_t4(const double *t, int a, int ao, int lc, int lr0) {
+  const double *p = t + t_block(a, ao) + lc * 18 + lr0;
+  const f64x2 lo = *reinterpret_cast<const f64x2 *>(p);
+  const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 2);
+  return f64x4{lo.x, lo.y, hi.x, hi.y};
+}
+
+// Y (unit lower trapezoidal in its top 64 rows, zero past the panel's last
+// row) and T of `leaf` into LDS; every thread of the workgroup takes part.
+// Two rounds of eight 16-byte loads per thread keep the staging registers few
+// (the next job's C is in flight meanwhile).
+__device__ __forceinline__ void res_stage(ResSmem &sm, const UpdateParams &u, int leaf, int tid) {
+  // Y: thread tid moves the row pair lr of columns col0 + 4s, s = 0..15, from
+  // one base address and a uniform stride (nothing per s to keep live)
+  const int64_t row0 = (int64_t)leaf * kResRows;
+  const bool full = row0 + kResRows <= u.m;
+  const int lr = 2 * (tid & 127), col0 = tid >> 7;
+  const int64_t g = row0 + lr;
+  const double *src = u.Y + g + (int64_t)col0 * u.ldy;
+  const int64_t step = 4 * u.ldy;
+  double *dst = sm.y + col0 * kResLd + lr;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    f64x2 v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const double *q = src + (8 * h + s) * step;
+      if (full) {
+        v[s] = *reinterpret_cast<const f64x2 *>(q);
+      } else {
+        v[s].x = (g < u.m) ? q[0] : 0.0;
+        v[s].y = (g + 1 < u.m) ? q[1] : 0.0;
+      }
+    }
+    // the row and column as opaque values: the masks below are recomputed at
+    // each staging instead of being kept live (spilled) across the job loop
+    int lrv = lr, c0v = col0;
+    asm volatile("" : "+v"(lrv), "+v"(c0v));
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int col = c0v + 4 * (8 * h + s);
+      f64x2 x = v[s];
+      if (lrv < kMaxB) {  // the leaf's top triangle: zero above the diagonal, 1 on it
+        x.x = (lrv > col) ? x.x : ((lrv == col) ? 1.0 : 0.0);
+        x.y = (lrv + 1 > col) ? x.y : ((lrv + 1 == col) ? 1.0 : 0.0);
+      }
+      *reinterpret_cast<f64x2 *>(dst + 4 * (8 * h + s) * kResLd) = x;
+    }
+  }
+  // T: the row pair tl of columns ct + 16s, kept where the block is on or above the diagonal
+  const int tl = 2 * (tid & 31), ct = tid >> 5;
+  const double *tg = u.T_leaf + (int64_t)leaf * kMaxB * kMaxB + tl + kMaxB * ct;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int a = tl >> 4, ao = s;  // column ct + 16 s lies in block column s
+    if (a <= ao)
+      *reinterpret_cast<f64x2 *>(sm.t + t_block(a, ao) + (ct & 15) * 18 + (tl & 15)) =
+          *reinterpret_cast<const f64x2 *>(tg + 16 * kMaxB * s);
+  }
+}
+
+// Slab x (rows row0 + 16x + 4lk .. +3) of column col of the job; cfast: the
+// whole job in range.  C is 16-byte aligned with an even leading dimension.
+__device__ __forceinline__ f64x4 res_load(const UpdateParams &u, int64_t row0, int64_t col, bool cfast, int x,
+                                          int lk) {
+  const int64_t grow = row0 + 16 * x + 4 * lk;
+  if (cfast) return ld_c4(u.C + grow + col * u.ldc);
+  return load_slab(u.C, u.ldc, grow, col, u.m, col < u.k, true);
+}
+
+__global__ void __launch_bounds__(kResThreads, 1) leaf_res_kernel(UpdateParams u, int ntiles, int jobs) {
+  __shared__ ResSmem sm;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int pl = pi16(li);
+  const int gw = xcd_range_index(blockIdx.x, gridDim.x);
+  const int j0 = (int)((int64_t)jobs * gw / gridDim.x);
+  const int j1 = (int)((int64_t)jobs * (gw + 1) / gridDim.x);
+  if (j0 >= j1) return;
+  // job j: leaf j / ntiles, columns tile * kResCols + 16 wave + li of C
+  auto job_row0 = [&](int j) { return (int64_t)(j / ntiles) * kResRows; };
+  auto job_col = [&](int j) { return (int64_t)(j % ntiles) * kResCols + 16 * wave + li; };
+  auto job_fast = [&](int j) {
+    return job_row0(j) + kResRows <= u.m && (int64_t)(j % ntiles + 1) * kResCols <= u.k;
+  };
+  f64x4 acc[16];
+  {
+    const int64_t r0 = job_row0(j0), c0 = job_col(j0);
+    const bool f0 = job_fast(j0);
+#pragma unroll
+    for (int x = 0; x < 16; ++x) acc[x] = res_load(u, r0, c0, f0, x, lk);
+  }
+  int cur = -1;
+  for (int j = j0; j < j1; ++j) {
+    const int leaf = j / ntiles;
+    if (leaf != cur) {  // every wave is past the previous leaf's reads
+      __syncthreads();
+      res_stage(sm, u, leaf, tid);
+      __syncthreads();
+      cur = leaf;
+    }
+    const int64_t row0 = job_row0(j), col = job_col(j);
+    const bool cfast = job_fast(j);
+    const bool next = j + 1 < j1;
+    const int64_t nrow0 = next ? job_row0(j + 1) : 0, ncol = next ? job_col(j + 1) : 0;
+    const bool nfast = next && job_fast(j + 1);
+    // ---- W = Y^T C: partial sums over rows 0..127 and 128..255, then added
+    f64x4 p0[4], p1[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) p0[a] = p1[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (x < a) continue;  // rows above block a are zero
+        const f64x4 y = res_col4(sm.y, 16 * a + pl, 16 * x + 4 * lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (x < 8) p0[a] = mfma16x16x4(y[r], acc[x][r], p0[a]);
+          else p1[a] = mfma16x16x4(y[r], acc[x][r], p1[a]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one slab's operands live at a time
+    }
+    f64x4 w[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) w[a] = p0[a] + p1[a];
+    // ---- W <- -T^T W (blocks from the last one down, in place)
+#pragma unroll
+    for (int oo = 0; oo < 4; ++oo) {
+      const int ao = 3 - oo;
+      f64x4 t4 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (a > ao) continue;
+        const f64x4 t = res_t4(sm.t, a, ao, pl, 4 * lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t4 = mfma16x16x4(t[r], w[a][r], t4);
+      }
+      w[ao] = t4;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) w[a] = -w[a];
+    // ---- C += Y W' slab by slab; each final slab stored, the next job's loaded
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (x < a) continue;
+        const f64x4 y = res_row4(sm.y, 16 * x + pl, 16 * a + 4 * lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(y[r], w[a][r], acc[x]);
+      }
+      const int64_t grow = row0 + 16 * x + 4 * lk;
+      if (cfast)
+        st_c4(u.C + grow + col * u.ldc, acc[x]);
+      else
+        store_slab(u.C, u.ldc, grow, col, u.m, col < u.k, true, acc[x]);
+      if (next) acc[x] = res_load(u, nrow0, ncol, nfast, x, lk);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 // Q^T leaf updates of the K neighbouring leaves of one first-level group
 // (leaves g .. g + K - 1) on one tile, then that group's node (its rows were
 // just written by this workgroup, so no other workgroup is involved): one
@@ -672,6 +890,30 @@ __global__ void __launch_bounds__(kUThreads, node_wgs_per_cu<K>()) qt_tree_tile_
   scale_top_rows_own<NQ>(u, tile);
 }
 
+// The resident-reflector leaf pass serves full-width panels of 256-row leaves
+// whose C, Y and T allow 16-byte accesses, on at least one full job width.
+bool res_ok(const UpdateParams &u) {
+  return u.b == kMaxB && u.h == kResRows && u.k >= kResCols && aligned16(u.C) && u.ldc % 2 == 0 && aligned16(u.Y) &&
+         u.ldy % 2 == 0 && aligned16(u.T_leaf);
+}
+
+// Workgroups of the resident-reflector leaf pass (its LDS admits one per CU):
+// one per CU of the current device except 3/16 of them, which stay free for
+// the panel chain's kernels running beside the wide update (8192^2: 45.7 ms
+// with every CU taken, 45.0 with 48 of 256 left, 46.6 with 96); fewer if
+// there are fewer jobs.
+int res_grid() {
+  static int grid[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 208;
+  if (!grid[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    grid[dev] = std::max(1, n - n * 3 / 16);
+  }
+  return grid[dev];
+}
+
 template <int NQ, int RT, int K, bool F32>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   if (u.tickets && u.tiles <= kTreeTiles && u.L > 1) {
@@ -687,6 +929,11 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
     hipLaunchKernelGGL((leaf_group_kernel<NQ, RT, K, F32>), dim3((u.L + K - 1) / K * u.tiles), dim3(kUThreads), 0,
                        s, u);
     st0 = K;
+  } else if (NQ == 4 && RT == 16 && !F32 && res_ok(u)) {
+    const int ntiles = (int)((u.k + kResCols - 1) / kResCols);
+    const int jobs = u.L * ntiles;
+    const int grid = std::min(jobs, res_grid());
+    hipLaunchKernelGGL(leaf_res_kernel, dim3(grid), dim3(kResThreads), 0, s, u, ntiles, jobs);
   } else {
     hipLaunchKernelGGL((leaf_kernel<NQ, RT, true, F32>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
   }

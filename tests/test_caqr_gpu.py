@@ -52,6 +52,25 @@ def test_invariants(arity):
     assert oracle.orthogonality_error(Q) <= 1e-13
 
 
+def test_resident_leaf_pass_matches_per_tile_pass():
+    """The wide update's leaf pass runs with each leaf's reflectors resident in
+    LDS where C allows 16-byte accesses (even leading dimension), else one
+    workgroup per leaf and 32-column tile; both form the same products in the
+    same order, so the factorizations are bitwise equal (partial last leaf and
+    partial last tile included)."""
+    require_gpu()
+    banner("caqr: resident leaf pass vs per-tile leaf pass, 3000 x 700")
+    m, n = 3000, 700
+    A = inputs.gaussian(m, n, 95)
+    F1, _ = caqr_gpu(A)
+    P = torch.zeros((n, m + 1), dtype=torch.float64, device="cuda").t()[:m, :]  # leading dimension m + 1
+    P.copy_(torch.as_tensor(A, device="cuda"))
+    F2 = caqr.caqr(P)
+    torch.cuda.synchronize()
+    assert np.array_equal(factored(F1), P.cpu().numpy())
+    F2.close()
+
+
 def test_determinism():
     require_gpu()
     A = inputs.gaussian(2000, 1500, 92)
