@@ -614,9 +614,9 @@ def main():
     pan_gbs = pan_bytes / (pan_ms * 1e-3) / 1e9 if pan_ms > 0 else 0.0
     pan_tflops = sum(panel_flops(e["rows"], e["width"]) for e in pan) / (pan_ms * 1e-3) / 1e12 if pan_ms > 0 else 0.0
     roof_update = {
-        "kernel": "trailing update call Q_s^T C of the columns beyond the next panel: leaf_kernel (one "
-                  "workgroup per leaf and 32-column tile) + one node_level_kernel per tree level + "
-                  "scale_rows_kernel",
+        "kernel": "trailing update call Q_s^T C of the columns beyond the next panel: leaf_res_kernel "
+                  "(each leaf's Y and T resident in LDS, one workgroup per CU over 128-column tiles) + one "
+                  "node_level_kernel per tree level + scale_rows_kernel",
         "bound": "mfma",
         "achieved": round(upd_achieved, 3),
         "peak": PEAK_FP64_TFLOPS,

@@ -801,6 +801,210 @@ __global__ void __launch_bounds__(kResThreads, 1) leaf_res_kernel(UpdateParams u
   }
 }
 
+// ---- Q^T updates of one tree level's 4-ary nodes with the node's V_1..V_3
+// and T resident in LDS (b = 64, FP64), the same scheme as leaf_res_kernel:
+// a workgroup of eight waves takes a contiguous run of jobs (node, 128-column
+// tile), staging V and T once per node it visits; wave w holds the top 64
+// rows of every member for columns 16w..16w+15.  The products are formed in
+// the order of node_update_k (partial sums of rows 0..31 and 32..63 of the
+// members added, T applied, then C_0 -= W' and C_t -= V_t W'), so the result
+// is bitwise that of node_level_kernel.
+constexpr int kNodeLd = kMaxB + 2;
+
+struct NodeResSmem {
+  alignas(16) double v[3][kMaxB * kNodeLd];  // V_1..V_3, column-major
+  alignas(16) double t[10 * kTBlk];
+};
+
+__device__ __forceinline__ f64x4 node_col4(const double *v, int col, int row0) {
+  const double *p = v + col * kNodeLd + row0;
+  const f64x2 lo = *reinterpret_cast<const f64x2 *>(p);
+  const f64x2 hi = *reinterpret_cast<const f64x2 *>(p + 2);
+  return f64x4{lo.x, lo.y, hi.x, hi.y};
+}
+
+__device__ __forceinline__ f64x4 node_row4(const double *v, int row, int col0) {
+  const double *p = v + col0 * kNodeLd + row;
+  return f64x4{p[0], p[kNodeLd], p[2 * kNodeLd], p[3 * kNodeLd]};
+}
+
+// V_t (upper triangular with its diagonal, zero past the panel's last row) of
+// members t = 1 .. cnt-1 of the node of survivor g at stride s, and the node's T.
+__device__ __forceinline__ void node_res_stage(NodeResSmem &sm, const UpdateParams &u, int g, int s, int cnt,
+                                               int tid) {
+  const int lr = 2 * (tid & 31), col0 = tid >> 5;  // row pair lr of columns col0 + 16 q, q = 0..3
+  int lrv = lr, c0v = col0;
+  asm volatile("" : "+v"(lrv), "+v"(c0v));
+#pragma unroll
+  for (int t = 1; t < 4; ++t) {
+    if (t >= cnt) break;
+    const int64_t g0 = (int64_t)(g + t * s) * u.h + lr;
+    const double *src = u.Y + g0 + (int64_t)col0 * u.ldy;
+    const bool full = g0 + 1 < u.m;
+    f64x2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double *p = src + (int64_t)(16 * q) * u.ldy;
+      if (full) {
+        v[q] = *reinterpret_cast<const f64x2 *>(p);
+      } else {
+        v[q].x = (g0 < u.m) ? p[0] : 0.0;
+        v[q].y = 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = c0v + 16 * q;
+      f64x2 x = v[q];
+      x.x = (lrv <= col) ? x.x : 0.0;
+      x.y = (lrv + 1 <= col) ? x.y : 0.0;
+      *reinterpret_cast<f64x2 *>(sm.v[t - 1] + col * kNodeLd + lr) = x;
+    }
+  }
+  const double *tg = u.T_node + (int64_t)(g + s) * kMaxB * kMaxB + lr + kMaxB * col0;
+  // T: the row pair lr of columns col0 + 16 q, kept where the block is on or above the diagonal
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int a = lr >> 4, ao = q;
+    if (a <= ao)
+      *reinterpret_cast<f64x2 *>(sm.t + t_block(a, ao) + col0 * 18 + (lr & 15)) =
+          *reinterpret_cast<const f64x2 *>(tg + 16 * kMaxB * q);
+  }
+}
+
+__global__ void __launch_bounds__(kResThreads, 1) node_res_kernel(UpdateParams u, int ntiles, int jobs) {
+  constexpr int K = 4;
+  __shared__ NodeResSmem sm;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int pl = pi16(li);
+  const int s = u.stride;
+  const int gw = xcd_range_index(blockIdx.x, gridDim.x);
+  const int j0 = (int)((int64_t)jobs * gw / gridDim.x);
+  const int j1 = (int)((int64_t)jobs * (gw + 1) / gridDim.x);
+  if (j0 >= j1) return;
+  // job j: node j / ntiles (survivor g = K s (j / ntiles)), columns tile * kResCols + 16 wave + li
+  auto job_g = [&](int j) { return K * s * (j / ntiles); };
+  auto job_col = [&](int j) { return (int64_t)(j % ntiles) * kResCols + 16 * wave + li; };
+  auto job_cnt = [&](int j) { return group_members(job_g(j), s, K, u.L); };
+  auto job_fast = [&](int j) {
+    return (int64_t)(job_g(j) + (job_cnt(j) - 1) * s) * u.h + kMaxB <= u.m &&
+           (int64_t)(j % ntiles + 1) * kResCols <= u.k;
+  };
+  auto load = [&](int j, int t, int x) {
+    const int64_t rt = (int64_t)(job_g(j) + t * s) * u.h;
+    const int64_t col = job_col(j);
+    const int64_t grow = rt + 16 * x + 4 * lk;
+    if (job_fast(j)) return ld_c4(u.C + grow + col * u.ldc);
+    return load_slab(u.C, u.ldc, grow, col, min<int64_t>(u.m, rt + u.b), col < u.k, true);
+  };
+  f64x4 c[K][4];
+  {
+    const int cnt0 = job_cnt(j0);
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (t < cnt0) c[t][x] = load(j0, t, x);
+  }
+  int cur = -1;
+  for (int j = j0; j < j1; ++j) {
+    const int node = j / ntiles;
+    const int g = job_g(j), cnt = job_cnt(j);
+    const int64_t col = job_col(j);
+    const bool cfast = job_fast(j);
+    const bool next = j + 1 < j1;
+    if (cnt >= 2 && node != cur) {  // every wave is past the previous node's reads
+      __syncthreads();
+      node_res_stage(sm, u, g, s, cnt, tid);
+      __syncthreads();
+      cur = node;
+    }
+    if (cnt >= 2) {
+      // ---- W = C_0 + sum_t V_t^T C_t: partial sums over rows 0..31 and 32..63
+      f64x4 p0[4], p1[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) p0[a] = p1[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 1; t < K; ++t) {
+        if (t >= cnt) break;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            if (x > a) continue;  // V upper triangular
+            const f64x4 v = node_col4(sm.v[t - 1], 16 * a + pl, 16 * x + 4 * lk);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (x < 2) p0[a] = mfma16x16x4(v[r], c[t][x][r], p0[a]);
+              else p1[a] = mfma16x16x4(v[r], c[t][x][r], p1[a]);
+            }
+          }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      f64x4 w[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (a < 2) p0[a] += c[0][a];
+        else p1[a] += c[0][a];
+        w[a] = p0[a] + p1[a];
+      }
+      // ---- W <- T^T W (blocks from the last one down, in place)
+#pragma unroll
+      for (int oo = 0; oo < 4; ++oo) {
+        const int ao = 3 - oo;
+        f64x4 t4 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a > ao) continue;
+          const f64x4 tt = res_t4(sm.t, a, ao, pl, 4 * lk);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) t4 = mfma16x16x4(tt[r], w[a][r], t4);
+        }
+        w[ao] = t4;
+      }
+      // ---- C_0 -= W';  C_t -= V_t W', each slab stored when final
+#pragma unroll
+      for (int x = 0; x < 4; ++x) c[0][x] -= w[x];
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        if (t >= cnt) break;
+        const int64_t rt = (int64_t)(g + t * s) * u.h;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          if (t > 0) {
+            f64x4 acc = c[t][x];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              if (a < x) continue;
+              const f64x4 v = node_row4(sm.v[t - 1], 16 * x + pl, 16 * a + 4 * lk);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc = mfma16x16x4(-v[r], w[a][r], acc);
+            }
+            c[t][x] = acc;
+          }
+          const int64_t grow = rt + 16 * x + 4 * lk;
+          if (cfast)
+            st_c4(u.C + grow + col * u.ldc, c[t][x]);
+          else
+            store_slab(u.C, u.ldc, grow, col, min<int64_t>(u.m, rt + u.b), col < u.k, true, c[t][x]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (next) {
+      const int cn = job_cnt(j + 1);
+#pragma unroll
+      for (int t = 0; t < K; ++t)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          if (t < cn) c[t][x] = load(j + 1, t, x);
+    }
+  }
+}
+
 // Q^T leaf updates of the K neighbouring leaves of one first-level group
 // (leaves g .. g + K - 1) on one tile, then that group's node (its rows were
 // just written by this workgroup, so no other workgroup is involved): one
@@ -897,6 +1101,13 @@ bool res_ok(const UpdateParams &u) {
          u.ldy % 2 == 0 && aligned16(u.T_leaf);
 }
 
+// The resident node levels: 4-ary nodes of full-width panels, C, Y and T
+// allowing 16-byte accesses, at least one full job width.
+bool node_res_ok(const UpdateParams &u) {
+  return u.b == kMaxB && u.k >= kResCols && aligned16(u.C) && u.ldc % 2 == 0 && aligned16(u.Y) && u.ldy % 2 == 0 &&
+         aligned16(u.T_node);
+}
+
 // Workgroups of the resident-reflector leaf pass (its LDS admits one per CU):
 // one per CU of the current device except 3/16 of them, which stay free for
 // the panel chain's kernels running beside the wide update (8192^2: 45.7 ms
@@ -941,7 +1152,13 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
     UpdateParams v = u;
     v.stride = st;
     const int per = (u.L - st + K * st - 1) / (K * st);
-    hipLaunchKernelGGL((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
+    if (K == 4 && NQ == 4 && node_res_ok(u)) {
+      const int ntiles = (int)((u.k + kResCols - 1) / kResCols);
+      const int jobs = per * ntiles;
+      hipLaunchKernelGGL(node_res_kernel, dim3(std::min(jobs, res_grid())), dim3(kResThreads), 0, s, v, ntiles, jobs);
+    } else {
+      hipLaunchKernelGGL((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
+    }
   }
   hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
   return hipGetLastError();

@@ -52,15 +52,17 @@ def test_invariants(arity):
     assert oracle.orthogonality_error(Q) <= 1e-13
 
 
-def test_resident_leaf_pass_matches_per_tile_pass():
-    """The wide update's leaf pass runs with each leaf's reflectors resident in
-    LDS where C allows 16-byte accesses (even leading dimension), else one
-    workgroup per leaf and 32-column tile; both form the same products in the
-    same order, so the factorizations are bitwise equal (partial last leaf and
-    partial last tile included)."""
+@pytest.mark.parametrize("m", [3000, 2850])
+def test_resident_passes_match_per_tile_passes(m):
+    """The wide update's leaf pass and node levels run with the reflectors of
+    each leaf (node) resident in LDS where C allows 16-byte accesses (even
+    leading dimension), else one workgroup per leaf (node) and 32-column tile;
+    both form the same products in the same order, so the factorizations are
+    bitwise equal (partial last leaf, a node member with fewer than 64 rows
+    (m = 2850), nodes of 3 members and partial last tiles included)."""
     require_gpu()
-    banner("caqr: resident leaf pass vs per-tile leaf pass, 3000 x 700")
-    m, n = 3000, 700
+    banner(f"caqr: resident passes vs per-tile passes, {m} x 700")
+    n = 700
     A = inputs.gaussian(m, n, 95)
     F1, _ = caqr_gpu(A)
     P = torch.zeros((n, m + 1), dtype=torch.float64, device="cuda").t()[:m, :]  # leading dimension m + 1
