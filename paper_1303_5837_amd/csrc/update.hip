@@ -965,9 +965,14 @@ __global__ void __launch_bounds__(kResThreads, 1) node_res_kernel(UpdateParams u
         }
         w[ao] = t4;
       }
-      // ---- C_0 -= W';  C_t -= V_t W', each slab stored when final
+      // ---- C_0 -= W';  C_t -= V_t W', each slab stored when final.  At the
+      // top level (the root, survivor 0) the panel's top rows also take D.
 #pragma unroll
       for (int x = 0; x < 4; ++x) c[0][x] -= w[x];
+      if (K * s >= u.L) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) c[0][x] *= ld_c4(u.d + 16 * x + 4 * lk);
+      }
 #pragma unroll
       for (int t = 0; t < K; ++t) {
         if (t >= cnt) break;
@@ -1105,7 +1110,7 @@ bool res_ok(const UpdateParams &u) {
 // allowing 16-byte accesses, at least one full job width.
 bool node_res_ok(const UpdateParams &u) {
   return u.b == kMaxB && u.k >= kResCols && aligned16(u.C) && u.ldc % 2 == 0 && aligned16(u.Y) && u.ldy % 2 == 0 &&
-         aligned16(u.T_node);
+         aligned16(u.T_node) && aligned16(u.d);
 }
 
 // Workgroups of the resident-reflector leaf pass (its LDS admits one per CU):
@@ -1148,11 +1153,12 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   } else {
     hipLaunchKernelGGL((leaf_kernel<NQ, RT, true, F32>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
   }
+  const bool res_levels = K == 4 && NQ == 4 && node_res_ok(u);  // the top one also applies D
   for (int st = st0; st < u.L; st *= K) {
     UpdateParams v = u;
     v.stride = st;
     const int per = (u.L - st + K * st - 1) / (K * st);
-    if (K == 4 && NQ == 4 && node_res_ok(u)) {
+    if (res_levels) {
       const int ntiles = (int)((u.k + kResCols - 1) / kResCols);
       const int jobs = per * ntiles;
       hipLaunchKernelGGL(node_res_kernel, dim3(std::min(jobs, res_grid())), dim3(kResThreads), 0, s, v, ntiles, jobs);
@@ -1160,7 +1166,7 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
       hipLaunchKernelGGL((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
     }
   }
-  hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
+  if (!(res_levels && u.L > 1)) hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
   return hipGetLastError();
 }
 
