@@ -86,6 +86,15 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
   }
   stage_store(st[0], sm.buf[0], tid);
   __syncthreads();
+  // The wave's block pairs (a, c), fixed for the whole loop; a wave with fewer
+  // than PW pairs repeats its last one (result unused).  Every product is
+  // issued unconditionally -- slabs of zeros (a leaf's top chunk is unit lower
+  // trapezoidal, every V_t upper triangular) add exact zeros -- so that the
+  // PW independent accumulations interleave instead of running as one
+  // dependent MFMA chain after another.
+  int pa[PW], pc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) block_pair<NQ>(min(wave + 4 * q, NP - 1), pa[q], pc[q]);
   f64x4 g[PW];
 #pragma unroll
   for (int q = 0; q < PW; ++q) g[q] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -94,21 +103,17 @@ __global__ void __launch_bounds__(kThreads) form_t_kernel(FormTParams f) {
     if (c >= nch) break;
     const double *ys = sm.buf[c & 1];
 #pragma unroll
-    for (int q = 0; q < PW; ++q) {
-      const int p = wave + 4 * q;
-      if (p >= NP) continue;
-      int a, cc;
-      block_pair<NQ>(p, a, cc);
+    for (int tt = 0; tt < 4; ++tt) {
+      f64x4 ya[PW], yc[PW];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        // slabs that hold only zeros of both blocks are skipped (a leaf's
-        // top chunk is unit lower trapezoidal, every V_t upper triangular)
-        if (is_leaf ? (c == 0 && tt < cc) : tt > a) continue;
-        const f64x4 ya = lds_col4(ys, 16 * a + li, 16 * tt + 4 * lk);
-        const f64x4 yc = lds_col4(ys, 16 * cc + li, 16 * tt + 4 * lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) g[q] = mfma16x16x4(ya[r], yc[r], g[q]);
+      for (int q = 0; q < PW; ++q) {
+        ya[q] = lds_col4(ys, 16 * pa[q] + li, 16 * tt + 4 * lk);
+        yc[q] = lds_col4(ys, 16 * pc[q] + li, 16 * tt + 4 * lk);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < PW; ++q) g[q] = mfma16x16x4(ya[q][r], yc[q][r], g[q]);
     }
     if (c + 1 < 4 && c + 1 < nch) {
       if (!is_leaf) stage_fix<kNodeV>(st[c + 1 < 4 ? c + 1 : 3], 0, tid);  // each V_t is a triangle

@@ -5,9 +5,8 @@
 // solved column by column from the bottom up,
 //     T(i, j) = -tau_i * sum_{i<k<=j} G(i, k) T(k, j),   T(j, j) = tau_j,
 // (which also holds for tau_i = 0), and the blocks above the diagonal follow
-// block column by block column, T(0:c0, blk) = -T(0:c0, 0:c0) (G(0:c0, blk) T(blk, blk)).
-// Every loop bound is a compile-time constant (masks instead of bounds), so
-// the LDS reads are independent and pipelined.
+// block column by block column, T(0:c0, blk) = -T(0:c0, 0:c0) (G(0:c0, blk) T(blk, blk)),
+// as 16x16 block products on MFMA.
 #pragma once
 
 #include "device_common.hpp"
@@ -46,45 +45,47 @@ __device__ __forceinline__ void form_t_lds(int b, const double *G, double *T, co
   }
   __syncthreads();
   if (NQ == 1) return;
-  // X(:, blk) = G(0:c0, blk) T(blk, blk) for every block column, in one pass;
-  // X(i, jj) of block column bc is kept in T's free strictly-lower triangle at
-  // row c0 + jj, column i (< c0): disjoint for different bc, never read as T.
-#pragma unroll
-  for (int bc = 1; bc < NQ; ++bc) {
-    const int c0 = 16 * bc;
-#pragma unroll
-    for (int e = 0; e < bc; ++e) {
-      const int i = (tid >> 4) + 16 * e;
-      const int jj = tid & 15;
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll 4
-      for (int kk = 0; kk < 16; ++kk) {
-        const double g = G[i * ld + c0 + kk];
-        const double tv = (kk <= jj) ? T[(c0 + kk) * ld + c0 + jj] : 0.0;
-        if (kk & 1) s1 = fma(g, tv, s1);
-        else s0 = fma(g, tv, s0);
-      }
-      T[(c0 + jj) * ld + i] = s0 + s1;
+  // The blocks above the diagonal, as 16x16 block products on FP64 MFMA (each
+  // four 16x16x4 steps): lane (i, k) = (lane % 16, lane / 16) supplies A(i, k)
+  // and B(k, i); result (4r + lane / 16, lane % 16) in register r.
+  const int li = lane & 15, lk = lane >> 4;
+  // X(e, bc) = G(e, bc) T(bc, bc) for every block e < bc (six products over the
+  // four waves), kept in T's free strictly-lower triangle: X(i, jj) of block
+  // column bc at row 16 bc + jj, column i (< 16 bc); never read as T.
+  for (int p = wave; p < NQ * (NQ - 1) / 2; p += 4) {
+    int bc = 1, e = p;
+    while (e >= bc) {
+      e -= bc;
+      ++bc;
     }
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kk = 4 * s4 + lk;
+      acc = mfma16x16x4(G[(16 * e + li) * ld + 16 * bc + kk], T[(16 * bc + kk) * ld + 16 * bc + li], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * bc + li) * ld + 16 * e + 4 * r + lk] = acc[r];
   }
   __syncthreads();
-  // T(0:c0, blk) = -T(0:c0, 0:c0) X(:, blk), block column by block column
+  // T(e, bc) = -sum_{f = e .. bc-1} T(e, f) X(f, bc), block column by block
+  // column (each needs the block columns left of it); wave e takes block row e
 #pragma unroll
   for (int bc = 1; bc < NQ; ++bc) {
-    const int c0 = 16 * bc;
+    const int e = wave;
+    if (e < bc) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int f = e; f < bc; ++f) {
 #pragma unroll
-    for (int e = 0; e < bc; ++e) {
-      const int i = (tid >> 4) + 16 * e;
-      const int jj = tid & 15;
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll 4
-      for (int k = 0; k < c0; ++k) {
-        const double tv = (k >= i) ? T[i * ld + k] : 0.0;
-        const double xv = T[(c0 + jj) * ld + k];
-        if (k & 1) s1 = fma(tv, xv, s1);
-        else s0 = fma(tv, xv, s0);
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int kk = 4 * s4 + lk;
+          // A(i, k) = T(16e + i, 16f + k) (upper triangular on the diagonal
+          // block, zero below it); B(k, j) = X(16f + k, j) = T(16bc + j, 16f + k)
+          acc = mfma16x16x4(T[(16 * e + li) * ld + 16 * f + kk], T[(16 * bc + li) * ld + 16 * f + kk], acc);
+        }
       }
-      T[i * ld + c0 + jj] = -(s0 + s1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T[(16 * e + 4 * r + lk) * ld + 16 * bc + li] = -acc[r];
     }
     __syncthreads();
   }
