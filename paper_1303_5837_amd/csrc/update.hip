@@ -303,19 +303,23 @@ __device__ __forceinline__ void node_update_k(const UpdateParams &u, int g, int 
   f64x4 w[NQ];
 #pragma unroll
   for (int a = 0; a < NQ; ++a) w[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // the NQ accumulations interleaved, every block unconditionally (V's
+  // blocks below its diagonal are staged zeros); each one's products in order
 #pragma unroll
   for (int t = 1; t < K; ++t) {
     if (t >= cnt) break;
 #pragma unroll
-    for (int a = 0; a < NQ; ++a)
+    for (int x = 0; x < 2; ++x) {
+      const int t2 = 2 * rh + x;
+      if (t2 >= NQ) continue;  // past the panel's width (slab not loaded)
+      f64x4 v[NQ];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const int t2 = 2 * rh + x;
-        if (t2 > a) continue;  // V upper triangular (also skips t2 >= NQ)
-        const f64x4 v = lds_col4(sm.buf[t - 1], 16 * a + pl, 16 * t2 + 4 * lk);
+      for (int a = 0; a < NQ; ++a) v[a] = lds_col4(sm.buf[t - 1], 16 * a + pl, 16 * t2 + 4 * lk);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(v[r], c[t][x][r], w[a]);
-      }
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) w[a] = mfma16x16x4(v[a][r], c[t][x][r], w[a]);
+    }
   }
 #pragma unroll
   for (int a = 0; a < NQ; ++a)
@@ -336,19 +340,34 @@ __device__ __forceinline__ void node_update_k(const UpdateParams &u, int g, int 
 #pragma unroll
   for (int t = 1; t < K; ++t) {
     if (t >= cnt) break;
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      const int t2 = 2 * rh + x;
-      if (t2 >= NQ) continue;
-      f64x4 acc = c[t][x];
+    if constexpr (NQ == 4) {
+      // both slabs interleaved, every block unconditionally (V's blocks below
+      // its diagonal are staged zeros); each slab's products in order
 #pragma unroll
       for (int a = 0; a < NQ; ++a) {
-        if (a < t2) continue;
-        const f64x4 v = lds_row4(sm.buf[t - 1], 16 * t2 + pl, 16 * a + 4 * lk);
+        const f64x4 v0 = lds_row4(sm.buf[t - 1], 32 * rh + pl, 16 * a + 4 * lk);
+        const f64x4 v1 = lds_row4(sm.buf[t - 1], 32 * rh + 16 + pl, 16 * a + 4 * lk);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc = mfma16x16x4(-v[r], w[a][r], acc);
+        for (int r = 0; r < 4; ++r) {
+          c[t][0] = mfma16x16x4(-v0[r], w[a][r], c[t][0]);
+          c[t][1] = mfma16x16x4(-v1[r], w[a][r], c[t][1]);
+        }
       }
-      c[t][x] = acc;
+    } else {
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int t2 = 2 * rh + x;
+        if (t2 >= NQ) continue;
+        f64x4 acc = c[t][x];
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+          if (a < t2) continue;
+          const f64x4 v = lds_row4(sm.buf[t - 1], 16 * t2 + pl, 16 * a + 4 * lk);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc = mfma16x16x4(-v[r], w[a][r], acc);
+        }
+        c[t][x] = acc;
+      }
     }
   }
 #pragma unroll
@@ -476,22 +495,24 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
     else
       stage_load_split<kDense>(st, u.T_leaf + (int64_t)leaf * 64 * 64, 64, 0, 0, 0, 0, 0, 0, true, tid);
     const double *ys = sm.buf[c & 1];
+    // every block a of the slab unconditionally (rows above block a are
+    // staged zeros and add exact zeros), so that the NQ accumulations
+    // interleave; each one's products stay in the same order
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
       const int x = 2 * c + tt;
-      const int xl = xl0 + x;  // slab index within the leaf
+      f64x4 y[NQ];
 #pragma unroll
-      for (int a = 0; a < NQ; ++a) {
-        if (xl < a) continue;  // rows above block a are zero
-        const f64x4 y = lds_col4(ys, 16 * a + pl, 32 * rh + 16 * tt + 4 * lk);
-        if constexpr (F32) {
+      for (int a = 0; a < NQ; ++a) y[a] = lds_col4(ys, 16 * a + pl, 32 * rh + 16 * tt + 4 * lk);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) w32[F32 ? a : 0] = mfma16x16x4_f32(y[r], acc[x][r], w32[F32 ? a : 0]);
-        } else {
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) w[a] = mfma16x16x4(y[r], acc[x][r], w[a]);
+        for (int a = 0; a < NQ; ++a) {
+          if constexpr (F32)
+            w32[F32 ? a : 0] = mfma16x16x4_f32(y[a][r], acc[x][r], w32[F32 ? a : 0]);
+          else
+            w[a] = mfma16x16x4(y[a][r], acc[x][r], w[a]);
         }
-      }
     }
     if (c + 1 < NCHUNK && 32 * (c + 1) < kMaxB)  // rows of the leaf's top triangle
       stage_fix_split<kLeafY>(st, 32 * (c + 1), HALF + 32 * (c + 1), tid);
@@ -531,20 +552,20 @@ __device__ __forceinline__ void leaf_update(const UpdateParams &u, int leaf, int
     }
     const double *ys = sm.buf[c & 1];
     f32x4 prod[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};  // FP32: Y W of this chunk
+    // both slabs of the chunk interleaved, every block a unconditionally
+    // (rows above block a are staged zeros); each slab's products in order
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int x = 2 * c + tt;
-      const int xl = xl0 + x;
+    for (int a = 0; a < NQ; ++a) {
+      const f64x4 y0 = lds_row4(ys, 32 * rh + pl, 16 * a + 4 * lk);
+      const f64x4 y1 = lds_row4(ys, 32 * rh + 16 + pl, 16 * a + 4 * lk);
 #pragma unroll
-      for (int a = 0; a < NQ; ++a) {
-        if (xl < a) continue;
-        const f64x4 y = lds_row4(ys, 32 * rh + 16 * tt + pl, 16 * a + 4 * lk);
+      for (int r = 0; r < 4; ++r) {
         if constexpr (F32) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) prod[tt] = mfma16x16x4_f32(y[r], w[a][r], prod[tt]);
+          prod[0] = mfma16x16x4_f32(y0[r], w[a][r], prod[0]);
+          prod[1] = mfma16x16x4_f32(y1[r], w[a][r], prod[1]);
         } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(y[r], w[a][r], acc[x]);
+          acc[2 * c] = mfma16x16x4(y0[r], w[a][r], acc[2 * c]);
+          acc[2 * c + 1] = mfma16x16x4(y1[r], w[a][r], acc[2 * c + 1]);
         }
       }
     }
