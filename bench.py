@@ -232,7 +232,7 @@ def batched_ls_line(reps=5, eta_sample=8):
 
 
 def served_lines(rates=(200, 500, 1000, 2000), duration=2.0, workers=8, pool=512, budget=64 << 30,
-                 eta_sample=8):
+                 eta_sample=8, plain=True):
     """Served least-squares stream: Poisson arrivals at each rate for `duration`
     seconds over a cached pool of problems (m log-uniform in [1024, 262144], n
     in [16, 512], kappa in [1e2, 1e6]); latency = completion - scheduled
@@ -266,7 +266,7 @@ def served_lines(rates=(200, 500, 1000, 2000), duration=2.0, workers=8, pool=512
 
     out = {"pool": pool, "pool_build_s": round(t_pool, 1), "duration_s": duration, "budget_bytes": budget,
            "request_gflop_mean": round(float(flops.mean()) / 1e9, 3)}
-    for label, w in (("served", workers), ("plain", 1)):
+    for label, w in (("served", workers), ("plain", 1)) if plain else (("served", workers),):
         S = caqr.Server(workers=w, budget_bytes=budget)
         for i in range(2 * w):  # first use of every worker's handle
             A, B = P[i % pool]
@@ -457,7 +457,7 @@ def tsqr_line(key):
             "algorithmic_GBps": round(gbs, 1), "pct_hbm_peak": round(100 * gbs / PEAK_HBM_GBS, 2)}
 
 
-def served_line_child(workers, hw_queues=16):
+def served_line_child(workers, hw_queues=16, which="served"):
     """The served stream in a child process started with GPU_MAX_HW_QUEUES =
     2 x workers (the HIP runtime reads it once, at initialization): each worker
     drives two streams, and with the default four hardware queues the workers'
@@ -465,11 +465,11 @@ def served_line_child(workers, hw_queues=16):
     import subprocess
 
     env = dict(os.environ, GPU_MAX_HW_QUEUES=str(max(hw_queues, 2 * workers)))
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--only", "served", "--served-workers",
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--only", which, "--served-workers",
                         str(workers)], env=env, capture_output=True, text=True, timeout=600)
     if r.returncode != 0:
         return {"error": f"served child exited {r.returncode}", "stderr_tail": r.stderr[-2000:]}
-    line = json.loads(r.stdout.strip().splitlines()[-1])["served"]
+    line = json.loads(r.stdout.strip().splitlines()[-1])[which]
     line["hw_queues"] = int(env["GPU_MAX_HW_QUEUES"])
     return line
 
@@ -518,8 +518,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--only", choices=["batched_tsqr", "batched_tsqr_f32", "batched_ls", "served", "tsqr_1Mx64",
-                                       "tsqr_4096x32", "mixed_ls"],
+    ap.add_argument("--only", choices=["batched_tsqr", "batched_tsqr_f32", "batched_ls", "served", "served_long",
+                                       "tsqr_1Mx64", "tsqr_4096x32", "mixed_ls"],
                     help="run one secondary workload alone and print its line (for profiling)")
     ap.add_argument("--served-workers", type=int, default=8, help="worker threads of the served stream's server")
     args = ap.parse_args()
@@ -540,6 +540,8 @@ def main():
     if args.only:
         fn = {"batched_tsqr": lambda: batched_line("f64"), "batched_tsqr_f32": lambda: batched_line("f32"),
               "batched_ls": batched_ls_line, "served": lambda: served_lines(workers=args.served_workers),
+              "served_long": lambda: served_lines(rates=(1000, 2000), duration=10.0, workers=args.served_workers,
+                                                  plain=False),
               "tsqr_1Mx64": lambda: tsqr_line("tsqr_1Mx64"), "tsqr_4096x32": lambda: tsqr_line("tsqr_4096x32"),
               "mixed_ls": mixed_ls_line}[args.only]
         print(json.dumps({args.only: fn()}))
@@ -697,6 +699,8 @@ def main():
         sec["batched_ls_2000_uneven"] = batched_ls_line()
         sec["mixed_ls_65536x1024"] = mixed_ls_line()
         sec["served_ls"] = served_line_child(args.served_workers)
+        # the two highest rates again over 10 s of arrivals (served configuration only)
+        sec["served_ls_10s"] = served_line_child(args.served_workers, which="served_long")
         out["secondary"] = sec
 
     if not args.no_cpu_baseline:
