@@ -614,12 +614,13 @@ __global__ void __launch_bounds__(kUThreads, 2) leaf_kernel(UpdateParams u) {
 // leaves, b = 64, FP64): the pass over the leaves of the wide trailing update.
 // A workgroup of eight waves (two per SIMD, one workgroup per CU) keeps Y and
 // T of one leaf in LDS and takes a contiguous run of jobs (leaf, 128-column
-// tile) in leaf-major order, so Y and T are staged once per leaf it visits.
-// Wave w holds columns 16w..16w+15 of the tile over all 256 rows (16 slabs in
+// tile) in leaf-major order (the jobs wholly inside C first, then the edge
+// jobs), so Y and T are staged once per leaf it visits.  Wave w holds columns 16w..16w+15 of the tile over all 256 rows (16 slabs in
 // the contiguous layout): W = Y^T C needs no exchange between waves, and no
 // barrier separates the waves within a job.  Each slab of C is stored as soon
 // as it is final and the next job's slab is loaded into its registers, so
-// the next job's C is in flight during this job's update.  The products are
+// the next job's C is in flight during this job's update (two slabs at a
+// time, their accumulations interleaved).  The products are
 // formed in the order of leaf_update (partial sums of rows 0..127 and
 // 128..255 added, T applied, then C += Y W' slab by slab), so the result is
 // bitwise that of leaf_kernel.
@@ -708,22 +709,90 @@ __device__ __forceinline__ void res_stage(ResSmem &sm, const UpdateParams &u, in
   // T: the row pair tl of columns ct + 16s, kept where the block is on or above the diagonal
   const int tl = 2 * (tid & 31), ct = tid >> 5;
   const double *tg = u.T_leaf + (int64_t)leaf * kMaxB * kMaxB + tl + kMaxB * ct;
+  // all four loads unconditional (the 64 x 64 block is whole), the LDS writes masked
+  f64x2 tv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) tv[s] = *reinterpret_cast<const f64x2 *>(tg + 16 * kMaxB * s);
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int a = tl >> 4, ao = s;  // column ct + 16 s lies in block column s
-    if (a <= ao)
-      *reinterpret_cast<f64x2 *>(sm.t + t_block(a, ao) + (ct & 15) * 18 + (tl & 15)) =
-          *reinterpret_cast<const f64x2 *>(tg + 16 * kMaxB * s);
+    if (a <= ao) *reinterpret_cast<f64x2 *>(sm.t + t_block(a, ao) + (ct & 15) * 18 + (tl & 15)) = tv[s];
   }
 }
 
-// Slab x (rows row0 + 16x + 4lk .. +3) of column col of the job; cfast: the
-// whole job in range.  C is 16-byte aligned with an even leading dimension.
-__device__ __forceinline__ f64x4 res_load(const UpdateParams &u, int64_t row0, int64_t col, bool cfast, int x,
-                                          int lk) {
-  const int64_t grow = row0 + 16 * x + 4 * lk;
-  if (cfast) return ld_c4(u.C + grow + col * u.ldc);
-  return load_slab(u.C, u.ldc, grow, col, u.m, col < u.k, true);
+// W = Y^T C of one job (partial sums over rows 0..127 and 128..255, then
+// added), then W <- -T^T W (blocks from the last one down, in place).
+__device__ __forceinline__ void res_form_w(const ResSmem &sm, const f64x4 (&acc)[16], f64x4 (&w)[4], int pl,
+                                           int lk) {
+  f64x4 p0[4], p1[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) p0[a] = p1[a] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int x = 0; x < 16; ++x) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (x < a) continue;  // rows above block a are zero
+      const f64x4 y = res_col4(sm.y, 16 * a + pl, 16 * x + 4 * lk);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (x < 8) p0[a] = mfma16x16x4(y[r], acc[x][r], p0[a]);
+        else p1[a] = mfma16x16x4(y[r], acc[x][r], p1[a]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one slab's operands live at a time
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) w[a] = p0[a] + p1[a];
+#pragma unroll
+  for (int oo = 0; oo < 4; ++oo) {
+    const int ao = 3 - oo;
+    f64x4 t4 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (a > ao) continue;
+      const f64x4 t = res_t4(sm.t, a, ao, pl, 4 * lk);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) t4 = mfma16x16x4(t[r], w[a][r], t4);
+    }
+    w[ao] = t4;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) w[a] = -w[a];
+}
+
+// Slab x of C += Y W'.
+__device__ __forceinline__ f64x4 res_apply_slab(const ResSmem &sm, f64x4 c, const f64x4 (&w)[4], int x, int pl,
+                                                int lk) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (x < a) continue;
+    const f64x4 y = res_row4(sm.y, 16 * x + pl, 16 * a + 4 * lk);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c = mfma16x16x4(y[r], w[a][r], c);
+  }
+  return c;
+}
+
+// Slabs x and x + 1 of C += Y W', their two accumulations interleaved (each
+// in the order of res_apply_slab).
+__device__ __forceinline__ void res_apply_slab2(const ResSmem &sm, f64x4 &c0, f64x4 &c1, const f64x4 (&w)[4], int x,
+                                                int pl, int lk) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (x + 1 < a) continue;
+    const f64x4 y1 = res_row4(sm.y, 16 * (x + 1) + pl, 16 * a + 4 * lk);
+    if (x >= a) {
+      const f64x4 y0 = res_row4(sm.y, 16 * x + pl, 16 * a + 4 * lk);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        c0 = mfma16x16x4(y0[r], w[a][r], c0);
+        c1 = mfma16x16x4(y1[r], w[a][r], c1);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c1 = mfma16x16x4(y1[r], w[a][r], c1);
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kResThreads, 1) leaf_res_kernel(UpdateParams u, int ntiles, int jobs) {
@@ -737,86 +806,74 @@ __global__ void __launch_bounds__(kResThreads, 1) leaf_res_kernel(UpdateParams u
   const int j0 = (int)((int64_t)jobs * gw / gridDim.x);
   const int j1 = (int)((int64_t)jobs * (gw + 1) / gridDim.x);
   if (j0 >= j1) return;
-  // job j: leaf j / ntiles, columns tile * kResCols + 16 wave + li of C
-  auto job_row0 = [&](int j) { return (int64_t)(j / ntiles) * kResRows; };
-  auto job_col = [&](int j) { return (int64_t)(j % ntiles) * kResCols + 16 * wave + li; };
-  auto job_fast = [&](int j) {
-    return job_row0(j) + kResRows <= u.m && (int64_t)(j % ntiles + 1) * kResCols <= u.k;
-  };
+  // Jobs (leaf, 128-column tile), the ones wholly inside C first, leaf-major
+  // (jobs [0, jm): leaf j / ntf, tile j % ntf), then the edge jobs: the last
+  // tile of each full leaf when k is not a multiple of 128, and the tiles of
+  // the last leaf when it is short.  The first run has no branch around its
+  // loads and stores, so the compiler counts the outstanding memory
+  // operations exactly and storing a slab, then loading the next job's slab
+  // into its registers, waits for nothing; the bounds-checked edge jobs run
+  // after it, in a loop of their own.
+  const int ntf = (int)(u.k / kResCols);
+  const int lf = (int)(u.m / kResRows);
+  const bool ce = ntf < ntiles;
+  const int jm = lf * ntf;
+  const int je = jm + (ce ? lf : 0);
+  double *const cw = u.C + 4 * lk + (int64_t)(16 * wave + li) * u.ldc;  // this lane's row 4lk of column 16w + li
+  auto job_c = [&](int j) { return cw + (int64_t)(j / ntf) * kResRows + (int64_t)(j % ntf) * kResCols * u.ldc; };
   f64x4 acc[16];
-  {
-    const int64_t r0 = job_row0(j0), c0 = job_col(j0);
-    const bool f0 = job_fast(j0);
-#pragma unroll
-    for (int x = 0; x < 16; ++x) acc[x] = res_load(u, r0, c0, f0, x, lk);
-  }
   int cur = -1;
-  for (int j = j0; j < j1; ++j) {
-    const int leaf = j / ntiles;
-    if (leaf != cur) {  // every wave is past the previous leaf's reads
+  const int jm1 = min(j1, jm);
+  if (j0 < jm1) {
+    {
+      const double *cp = job_c(j0);
+#pragma unroll
+      for (int x = 0; x < 16; ++x) acc[x] = ld_c4(cp + 16 * x);
+    }
+    for (int j = j0; j < jm1; ++j) {
+      const int leaf = j / ntf;
+      if (leaf != cur) {  // every wave is past the previous leaf's reads
+        __syncthreads();
+        res_stage(sm, u, leaf, tid);
+        __syncthreads();
+        cur = leaf;
+      }
+      double *cp = job_c(j);
+      f64x4 w[4];
+      res_form_w(sm, acc, w, pl, lk);
+      // ---- C += Y W' slab by slab; each final slab stored and the next job's
+      // slab loaded into its registers (on the last job a value never used,
+      // from this job's own columns)
+      const double *np = (j + 1 < jm1) ? job_c(j + 1) : cp;
+#pragma unroll
+      for (int x = 0; x < 16; x += 2) {
+        res_apply_slab2(sm, acc[x], acc[x + 1], w, x, pl, lk);
+        st_c4(cp + 16 * x, acc[x]);
+        st_c4(cp + 16 * x + 16, acc[x + 1]);
+        acc[x] = ld_c4(np + 16 * x);
+        acc[x + 1] = ld_c4(np + 16 * x + 16);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  for (int j = max(j0, jm); j < j1; ++j) {
+    const int leaf = (j < je) ? j - jm : lf;
+    const int tile = (j < je) ? ntf : j - je;
+    if (leaf != cur) {
       __syncthreads();
       res_stage(sm, u, leaf, tid);
       __syncthreads();
       cur = leaf;
     }
-    const int64_t row0 = job_row0(j), col = job_col(j);
-    const bool cfast = job_fast(j);
-    const bool next = j + 1 < j1;
-    const int64_t nrow0 = next ? job_row0(j + 1) : 0, ncol = next ? job_col(j + 1) : 0;
-    const bool nfast = next && job_fast(j + 1);
-    // ---- W = Y^T C: partial sums over rows 0..127 and 128..255, then added
-    f64x4 p0[4], p1[4];
+    const int64_t row0 = (int64_t)leaf * kResRows, col = (int64_t)tile * kResCols + 16 * wave + li;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) p0[a] = p1[a] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int x = 0; x < 16; ++x) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        if (x < a) continue;  // rows above block a are zero
-        const f64x4 y = res_col4(sm.y, 16 * a + pl, 16 * x + 4 * lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (x < 8) p0[a] = mfma16x16x4(y[r], acc[x][r], p0[a]);
-          else p1[a] = mfma16x16x4(y[r], acc[x][r], p1[a]);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);  // one slab's operands live at a time
-    }
+    for (int x = 0; x < 16; ++x) acc[x] = load_slab(u.C, u.ldc, row0 + 16 * x + 4 * lk, col, u.m, col < u.k, true);
     f64x4 w[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) w[a] = p0[a] + p1[a];
-    // ---- W <- -T^T W (blocks from the last one down, in place)
-#pragma unroll
-    for (int oo = 0; oo < 4; ++oo) {
-      const int ao = 3 - oo;
-      f64x4 t4 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        if (a > ao) continue;
-        const f64x4 t = res_t4(sm.t, a, ao, pl, 4 * lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) t4 = mfma16x16x4(t[r], w[a][r], t4);
-      }
-      w[ao] = t4;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) w[a] = -w[a];
-    // ---- C += Y W' slab by slab; each final slab stored, the next job's loaded
+    res_form_w(sm, acc, w, pl, lk);
 #pragma unroll
     for (int x = 0; x < 16; ++x) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        if (x < a) continue;
-        const f64x4 y = res_row4(sm.y, 16 * x + pl, 16 * a + 4 * lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[x] = mfma16x16x4(y[r], w[a][r], acc[x]);
-      }
-      const int64_t grow = row0 + 16 * x + 4 * lk;
-      if (cfast)
-        st_c4(u.C + grow + col * u.ldc, acc[x]);
-      else
-        store_slab(u.C, u.ldc, grow, col, u.m, col < u.k, true, acc[x]);
-      if (next) acc[x] = res_load(u, nrow0, ncol, nfast, x, lk);
+      acc[x] = res_apply_slab(sm, acc[x], w, x, pl, lk);
+      store_slab(u.C, u.ldc, row0 + 16 * x + 4 * lk, col, u.m, col < u.k, true, acc[x]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
