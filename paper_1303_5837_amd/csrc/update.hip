@@ -824,37 +824,35 @@ __global__ void __launch_bounds__(kResThreads, 1) leaf_res_kernel(UpdateParams u
   f64x4 acc[16];
   int cur = -1;
   const int jm1 = min(j1, jm);
-  if (j0 < jm1) {
-    {
-      const double *cp = job_c(j0);
+  int j = (j0 < jm1) ? j0 : -1;
+  if (j >= 0) {
+    const double *cp = job_c(j);
 #pragma unroll
-      for (int x = 0; x < 16; ++x) acc[x] = ld_c4(cp + 16 * x);
+    for (int x = 0; x < 16; ++x) acc[x] = ld_c4(cp + 16 * x);
+  }
+  while (j >= 0) {
+    const int leaf = j / ntf;
+    if (leaf != cur) {  // every wave is past the previous leaf's reads
+      __syncthreads();
+      res_stage(sm, u, leaf, tid);
+      __syncthreads();
+      cur = leaf;
     }
-    for (int j = j0; j < jm1; ++j) {
-      const int leaf = j / ntf;
-      if (leaf != cur) {  // every wave is past the previous leaf's reads
-        __syncthreads();
-        res_stage(sm, u, leaf, tid);
-        __syncthreads();
-        cur = leaf;
-      }
-      double *cp = job_c(j);
-      f64x4 w[4];
-      res_form_w(sm, acc, w, pl, lk);
-      // ---- C += Y W' slab by slab; each final slab stored and the next job's
-      // slab loaded into its registers (on the last job a value never used,
-      // from this job's own columns)
-      const double *np = (j + 1 < jm1) ? job_c(j + 1) : cp;
+    double *cp = job_c(j);
+    f64x4 w[4];
+    res_form_w(sm, acc, w, pl, lk);
+    const int jn = (j + 1 < jm1) ? j + 1 : -1;
+    const double *np = (jn >= 0) ? job_c(jn) : cp;
 #pragma unroll
-      for (int x = 0; x < 16; x += 2) {
-        res_apply_slab2(sm, acc[x], acc[x + 1], w, x, pl, lk);
-        st_c4(cp + 16 * x, acc[x]);
-        st_c4(cp + 16 * x + 16, acc[x + 1]);
-        acc[x] = ld_c4(np + 16 * x);
-        acc[x + 1] = ld_c4(np + 16 * x + 16);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+    for (int x = 0; x < 16; x += 2) {
+      res_apply_slab2(sm, acc[x], acc[x + 1], w, x, pl, lk);
+      st_c4(cp + 16 * x, acc[x]);
+      st_c4(cp + 16 * x + 16, acc[x + 1]);
+      acc[x] = ld_c4(np + 16 * x);
+      acc[x + 1] = ld_c4(np + 16 * x + 16);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    j = jn;
   }
   for (int j = max(j0, jm); j < j1; ++j) {
     const int leaf = (j < je) ? j - jm : lf;
