@@ -618,7 +618,8 @@ def main():
     roof_update = {
         "kernel": "trailing update call Q_s^T C of the columns beyond the next panel: leaf_res_kernel "
                   "(each leaf's Y and T resident in LDS, one workgroup per CU over 128-column tiles) + one "
-                  "node_level_kernel per tree level + scale_rows_kernel",
+                  "node_res_kernel per tree level (each node's V and T resident in LDS; the root one also "
+                  "applies D)",
         "bound": "mfma",
         "achieved": round(upd_achieved, 3),
         "peak": PEAK_FP64_TFLOPS,

@@ -841,15 +841,19 @@ __global__ void __launch_bounds__(kResThreads, 1) leaf_res_kernel(UpdateParams u
     double *cp = job_c(j);
     f64x4 w[4];
     res_form_w(sm, acc, w, pl, lk);
+    // ---- C += Y W' two slabs at a time; each final slab stored and the next
+    // job's slab loaded into its registers (after the last job, a value never
+    // used: every slab's load reads this lane's first slab, which stays cached)
     const int jn = (j + 1 < jm1) ? j + 1 : -1;
     const double *np = (jn >= 0) ? job_c(jn) : cp;
+    const int ns = (jn >= 0) ? 16 : 0;
 #pragma unroll
     for (int x = 0; x < 16; x += 2) {
       res_apply_slab2(sm, acc[x], acc[x + 1], w, x, pl, lk);
       st_c4(cp + 16 * x, acc[x]);
       st_c4(cp + 16 * x + 16, acc[x + 1]);
-      acc[x] = ld_c4(np + 16 * x);
-      acc[x + 1] = ld_c4(np + 16 * x + 16);
+      acc[x] = ld_c4(np + ns * x);
+      acc[x + 1] = ld_c4(np + ns * (x + 1));
       __builtin_amdgcn_sched_barrier(0);
     }
     j = jn;
