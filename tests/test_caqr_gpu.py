@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_1303_5837_amd import caqr, inputs
-from tests._gpu import banner, caqr_gpu, factored, q_thin, require_gpu
+from tests._gpu import banner, caqr_gpu, factored, q_thin, require_gpu, tsqr_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -52,17 +52,18 @@ def test_invariants(arity):
     assert oracle.orthogonality_error(Q) <= 1e-13
 
 
-@pytest.mark.parametrize("m", [3000, 2850])
-def test_resident_passes_match_per_tile_passes(m):
+@pytest.mark.parametrize("m,n", [(3000, 700), (2850, 700), (2048, 640)])
+def test_resident_passes_match_per_tile_passes(m, n):
     """The wide update's leaf pass and node levels run with the reflectors of
     each leaf (node) resident in LDS where C allows 16-byte accesses (even
     leading dimension), else one workgroup per leaf (node) and 32-column tile;
     both form the same products in the same order, so the factorizations are
     bitwise equal (partial last leaf, a node member with fewer than 64 rows
-    (m = 2850), nodes of 3 members and partial last tiles included)."""
+    (m = 2850), nodes of 3 members and partial last tiles included; and leaf
+    passes with no edge job at all (2048 x 640: whole leaves and whole
+    128-column tiles in its first calls))."""
     require_gpu()
-    banner(f"caqr: resident passes vs per-tile passes, {m} x 700")
-    n = 700
+    banner(f"caqr: resident passes vs per-tile passes, {m} x {n}")
     A = inputs.gaussian(m, n, 95)
     F1, _ = caqr_gpu(A)
     P = torch.zeros((n, m + 1), dtype=torch.float64, device="cuda").t()[:m, :]  # leading dimension m + 1
@@ -71,6 +72,34 @@ def test_resident_passes_match_per_tile_passes(m):
     torch.cuda.synchronize()
     assert np.array_equal(factored(F1), P.cpu().numpy())
     F2.close()
+
+
+@pytest.mark.parametrize("m,k", [(200, 300), (1024, 256), (3000, 330)])
+def test_resident_apply_qt_matches_per_tile(m, k):
+    """Q^T of an m x 64 TSQR applied to C = [A, G] (m x k): the leaf pass with
+    the reflectors resident in LDS (even leading dimension) and the per-tile
+    leaf kernel (odd) agree bitwise, on a leaf pass of edge jobs only (m = 200,
+    one short leaf), one with none (1024 x 256: whole leaves and tiles) and one
+    with both; Q^T A is [R; 0] and Q Q^T C returns C."""
+    require_gpu()
+    banner(f"apply_q: resident leaf pass vs per-tile, {m} x 64 applied to {m} x {k}")
+    A = inputs.gaussian(m, 64, 96)
+    F, R = tsqr_gpu(A)
+    C0 = np.concatenate([A, np.random.default_rng(7).standard_normal((m, k - 64))], axis=1)
+    C1 = caqr.fortran(C0)
+    C2 = torch.zeros((k, m + 1), dtype=torch.float64, device="cuda").t()[:m, :]  # leading dimension m + 1
+    C2.copy_(torch.as_tensor(C0, device="cuda"))
+    F.apply_q(C1, caqr.OP_T)
+    F.apply_q(C2, caqr.OP_T)
+    torch.cuda.synchronize()
+    X = C1.cpu().numpy()
+    assert np.array_equal(X, C2.cpu().numpy())
+    assert oracle.rel_fro(X[:64, :64], R) <= 1e-13
+    assert np.abs(X[64:, :64]).max() <= 1e-13 * np.linalg.norm(A)
+    F.apply_q(C1, caqr.OP_N)
+    torch.cuda.synchronize()
+    assert oracle.rel_fro(C1.cpu().numpy(), C0) <= 1e-14
+    F.close()
 
 
 def test_determinism():
