@@ -811,9 +811,11 @@ __global__ void __launch_bounds__(kResThreads, 1) leaf_res_kernel(UpdateParams u
   // tile of each full leaf when k is not a multiple of 128, and the tiles of
   // the last leaf when it is short.  The first run has no branch around its
   // loads and stores, so the compiler counts the outstanding memory
-  // operations exactly and storing a slab, then loading the next job's slab
-  // into its registers, waits for nothing; the bounds-checked edge jobs run
-  // after it, in a loop of their own.
+  // operations exactly: storing a slab, then loading the next job's slab into
+  // its registers, waits for nothing, and (with the loop over the job index
+  // written as below) the W phase waits for the prefetched slabs one by one
+  // rather than for all of them.  The bounds-checked edge jobs run after it,
+  // in a loop of their own.
   const int ntf = (int)(u.k / kResCols);
   const int lf = (int)(u.m / kResRows);
   const bool ce = ntf < ntiles;
