@@ -568,11 +568,12 @@ def main():
         F.close()
     torch.cuda.synchronize()
 
-    # events bracket the panel factorizations (leaf QRs and the tree climb, one
-    # launch each, on the handle's stream) and the wide trailing-update calls
-    # (a leaf launch plus one launch per tree level, on the second stream):
-    # the two kernels whose rooflines the line reports
-    h.set_trace_kinds(["panel", "update_t_levels"])
+    # events bracket the wide trailing-update calls (a leaf launch plus one
+    # launch per tree level, on the second stream), the kernel whose roofline
+    # the line reports; the panel factorizations (on the critical chain, where
+    # the events' own cost would lengthen the step) are timed in the
+    # diagnostic step below
+    h.set_trace_kinds(["update_t_levels"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     events = []
@@ -599,6 +600,7 @@ def main():
     h.set_trace(True)
     F, e0, e1 = one_step()
     F.close()
+    full_ms = e0.elapsed_time(e1)
     full = h.take_trace()
     h.set_trace(False)
     chain = {}
@@ -610,7 +612,7 @@ def main():
     upd_ms = sum(e["ms"] for e in upd)
     upd_flops = sum(update_flops(e["rows"], e["cols"], e["width"], e["leaves"]) for e in upd)
     upd_achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
-    pan = [e for e in trace if e["kind"] == "panel"]
+    pan = [e for e in full if e["kind"] == "panel"]  # the diagnostic step (every launch bracketed)
     pan_bytes = sum(panel_bytes(e["rows"], e["width"]) for e in pan)
     pan_ms = sum(e["ms"] for e in pan)
     pan_gbs = pan_bytes / (pan_ms * 1e-3) / 1e9 if pan_ms > 0 else 0.0
@@ -645,12 +647,13 @@ def main():
         "traffic_algorithmic": round(pan_bytes / max(1, len(pan))),
         "algorithmic_bytes": "16 m_s b per panel (read the panel, write its Y and R)",
         "fp64_tflops": round(pan_tflops, 4),
-        "launches_per_step": len(pan) // max(1, args.steps),
+        "launches_per_step": len(pan),
         "avg_launch_ms": round(pan_ms / max(1, len(pan)), 5),
-        "share_of_step": round(pan_ms / max(1e-9, sum(step_ms)), 4),
+        "share_of_step": round(pan_ms / max(1e-9, full_ms), 4),
+        "timed": "one diagnostic step with every launch bracketed, after the timed steps",
         "bound_note": "latency: 64 sequential Householder steps per leaf and per tree level",
     }
-    panel_dominant = pan_ms >= upd_ms
+    panel_dominant = pan_ms >= upd_ms / max(1, args.steps)
 
     out = {
         "metric": "CAQR FP64 GFLOP/s (% peak); batched LS solves/s + p99 latency vs plain",

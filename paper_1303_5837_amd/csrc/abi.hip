@@ -194,14 +194,18 @@ hipEvent_t pool_event(caqr_handle_t h) {
 
 // Brackets one launch with events (on the stream it is launched on) when
 // tracing is on.
+// With bind, the scope's events are bound to the kernels launch_apply_qt
+// launches inside it (their own start and end times) instead of being
+// recorded on the stream around them.
 struct TraceScope {
   caqr_handle_t h;
   hipStream_t stream;
   TraceRec rec{};
   bool on;
+  bool bind;
   TraceScope(caqr_handle_t hh, int kind, int panel, int64_t rows, int64_t cols, int width, int leaves,
-             hipStream_t st = nullptr)
-      : h(hh), stream(st ? st : hh->stream), on(hh->trace && ((hh->trace_mask >> kind) & 1u)) {
+             hipStream_t st = nullptr, bool bind_launches = false)
+      : h(hh), stream(st ? st : hh->stream), on(hh->trace && ((hh->trace_mask >> kind) & 1u)), bind(bind_launches) {
     if (!on) return;
     rec.e.kind = kind;
     rec.e.panel = panel;
@@ -216,11 +220,17 @@ struct TraceScope {
       on = false;
       return;
     }
-    (void)hipEventRecord(rec.start, stream);
+    if (bind)
+      set_launch_trace(rec.start, rec.stop);
+    else
+      (void)hipEventRecord(rec.start, stream);
   }
   ~TraceScope() {
     if (!on) return;
-    (void)hipEventRecord(rec.stop, stream);
+    if (bind)
+      set_launch_trace(nullptr, nullptr);
+    else
+      (void)hipEventRecord(rec.stop, stream);
     h->trace_recs.push_back(rec);
   }
 };
@@ -469,7 +479,7 @@ caqr_status_t launch_trailing(caqr_handle_t h, caqr_factors_t F, int idx, int64_
   // the same test launch_apply_qt makes: one tree-climbing launch, or levels
   const bool one_launch = u.tickets && u.tiles <= kTreeTiles && u.L > 1;
   if (forced_fault(h)) return CAQR_ERR_DEVICE;
-  TraceScope ts(h, one_launch ? CAQR_TRACE_UPDATE_T : CAQR_TRACE_UPDATE_T_LEVELS, idx, p.m, k, p.b, p.L, st);
+  TraceScope ts(h, one_launch ? CAQR_TRACE_UPDATE_T : CAQR_TRACE_UPDATE_T_LEVELS, idx, p.m, k, p.b, p.L, st, true);
   return launch_apply_qt(u, st) == hipSuccess ? CAQR_SUCCESS : CAQR_ERR_DEVICE;
 }
 

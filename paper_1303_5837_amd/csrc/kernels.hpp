@@ -89,6 +89,11 @@ hipError_t launch_tsqr_tree_level(const PanelParams32 *probs, const int4 *nodes,
 // each (leaf, tile) workgroup climbs its tile's tree.
 hipError_t launch_apply_qt(const UpdateParams &u, hipStream_t s);
 
+// Bind the next launch_apply_qt on this thread to two events: start takes its
+// first kernel's start time, stop its last kernel's end time (no packets of
+// their own on the stream).  (nullptr, nullptr) unbinds.
+void set_launch_trace(hipEvent_t start, hipEvent_t stop);
+
 // C <- Q C for one panel: rows 0..b-1 scaled by D, the tree top-down (one
 // launch per level), then the leaves.
 hipError_t launch_apply_qn(const UpdateParams &u, hipStream_t s);

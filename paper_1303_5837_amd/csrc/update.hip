@@ -34,6 +34,7 @@
 // MFMA result layout holds row 4r + lane/16 in register r, so every product
 // whose output uses the contiguous layout reads its A operand at the permuted
 // row pi(lane%16) = 4*(lane%4) + (lane%16)/4 of the slab.
+#include <hip/hip_ext.h>
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -1212,10 +1213,26 @@ int res_grid() {
   return grid[dev];
 }
 
+// Trace events of the Q^T call being launched on this thread (set by the
+// caller around one call): the start event takes the first launch's start
+// time and the stop event each launch's end time (the last one stays), so
+// timing a call adds no packets of its own to the stream.
+thread_local hipEvent_t tl_trace_start = nullptr, tl_trace_stop = nullptr;
+
+template <typename Kern, typename... Args>
+void launch_traced(Kern kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  if (tl_trace_stop) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, tl_trace_start, tl_trace_stop, 0, args...);
+    tl_trace_start = nullptr;  // the first launch only
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+  }
+}
+
 template <int NQ, int RT, int K, bool F32>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   if (u.tickets && u.tiles <= kTreeTiles && u.L > 1) {
-    hipLaunchKernelGGL((qt_tree_tile_kernel<NQ, RT, K, F32>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
+    launch_traced((qt_tree_tile_kernel<NQ, RT, K, F32>), dim3(u.L * u.tiles), dim3(kUThreads), s, u);
     return hipGetLastError();
   }
   // binary trees: leaf pairs with the first level, then the tree bottom-up (one
@@ -1224,16 +1241,16 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   // reaches free CUs sooner), then every level by its own launch.
   int st0 = 1;
   if constexpr (K == 2) {
-    hipLaunchKernelGGL((leaf_group_kernel<NQ, RT, K, F32>), dim3((u.L + K - 1) / K * u.tiles), dim3(kUThreads), 0,
-                       s, u);
+    launch_traced((leaf_group_kernel<NQ, RT, K, F32>), dim3((u.L + K - 1) / K * u.tiles), dim3(kUThreads),
+                  s, u);
     st0 = K;
   } else if (NQ == 4 && RT == 16 && !F32 && res_ok(u)) {
     const int ntiles = (int)((u.k + kResCols - 1) / kResCols);
     const int jobs = u.L * ntiles;
     const int grid = std::min(jobs, res_grid());
-    hipLaunchKernelGGL(leaf_res_kernel, dim3(grid), dim3(kResThreads), 0, s, u, ntiles, jobs);
+    launch_traced(leaf_res_kernel, dim3(grid), dim3(kResThreads), s, u, ntiles, jobs);
   } else {
-    hipLaunchKernelGGL((leaf_kernel<NQ, RT, true, F32>), dim3(u.L * u.tiles), dim3(kUThreads), 0, s, u);
+    launch_traced((leaf_kernel<NQ, RT, true, F32>), dim3(u.L * u.tiles), dim3(kUThreads), s, u);
   }
   const bool res_levels = K == 4 && NQ == 4 && node_res_ok(u);  // the top one also applies D
   for (int st = st0; st < u.L; st *= K) {
@@ -1243,12 +1260,12 @@ hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
     if (res_levels) {
       const int ntiles = (int)((u.k + kResCols - 1) / kResCols);
       const int jobs = per * ntiles;
-      hipLaunchKernelGGL(node_res_kernel, dim3(std::min(jobs, res_grid())), dim3(kResThreads), 0, s, v, ntiles, jobs);
+      launch_traced(node_res_kernel, dim3(std::min(jobs, res_grid())), dim3(kResThreads), s, v, ntiles, jobs);
     } else {
-      hipLaunchKernelGGL((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), 0, s, v);
+      launch_traced((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), s, v);
     }
   }
-  if (!(res_levels && u.L > 1)) hipLaunchKernelGGL(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), 0, s, u);
+  if (!(res_levels && u.L > 1)) launch_traced(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), s, u);
   return hipGetLastError();
 }
 
@@ -1305,5 +1322,10 @@ hipError_t dispatch(const UpdateParams &u, bool trans, hipStream_t s) {
 
 hipError_t launch_apply_qt(const UpdateParams &u, hipStream_t s) { return dispatch(u, true, s); }
 hipError_t launch_apply_qn(const UpdateParams &u, hipStream_t s) { return dispatch(u, false, s); }
+
+void set_launch_trace(hipEvent_t start, hipEvent_t stop) {
+  tl_trace_start = start;
+  tl_trace_stop = stop;
+}
 
 }  // namespace caqr
