@@ -1215,14 +1215,15 @@ int res_grid() {
 
 // Trace events of the Q^T call being launched on this thread (set by the
 // caller around one call): the start event takes the first launch's start
-// time and the stop event each launch's end time (the last one stays), so
-// timing a call adds no packets of its own to the stream.
+// time and the stop event the last launch's end time, so timing a call adds
+// no packets of its own to the stream.
 thread_local hipEvent_t tl_trace_start = nullptr, tl_trace_stop = nullptr;
 
 template <typename Kern, typename... Args>
-void launch_traced(Kern kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
-  if (tl_trace_stop) {
-    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, tl_trace_start, tl_trace_stop, 0, args...);
+void launch_traced(Kern kernel, dim3 grid, dim3 block, hipStream_t s, bool last, Args... args) {
+  hipEvent_t stop = last ? tl_trace_stop : nullptr;
+  if (tl_trace_start || stop) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, tl_trace_start, stop, 0, args...);
     tl_trace_start = nullptr;  // the first launch only
   } else {
     hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
@@ -1232,40 +1233,42 @@ void launch_traced(Kern kernel, dim3 grid, dim3 block, hipStream_t s, Args... ar
 template <int NQ, int RT, int K, bool F32>
 hipError_t launch_qt_t(const UpdateParams &u, hipStream_t s) {
   if (u.tickets && u.tiles <= kTreeTiles && u.L > 1) {
-    launch_traced((qt_tree_tile_kernel<NQ, RT, K, F32>), dim3(u.L * u.tiles), dim3(kUThreads), s, u);
+    launch_traced((qt_tree_tile_kernel<NQ, RT, K, F32>), dim3(u.L * u.tiles), dim3(kUThreads), s, true, u);
     return hipGetLastError();
   }
+  const bool res_levels = K == 4 && NQ == 4 && node_res_ok(u);  // the top one also applies D
+  const bool scale = !(res_levels && u.L > 1);                   // D by its own launch
   // binary trees: leaf pairs with the first level, then the tree bottom-up (one
   // launch per level, nodes of a level in parallel), then D.  Wider nodes: one
   // workgroup per leaf (short workgroups, so that the concurrent panel chain
   // reaches free CUs sooner), then every level by its own launch.
-  int st0 = 1;
+  const int st0 = (K == 2) ? K : 1;  // the first level a level launch takes
+  const bool leaf_last = st0 >= u.L && !scale;
   if constexpr (K == 2) {
     launch_traced((leaf_group_kernel<NQ, RT, K, F32>), dim3((u.L + K - 1) / K * u.tiles), dim3(kUThreads),
-                  s, u);
-    st0 = K;
+                  s, leaf_last, u);
   } else if (NQ == 4 && RT == 16 && !F32 && res_ok(u)) {
     const int ntiles = (int)((u.k + kResCols - 1) / kResCols);
     const int jobs = u.L * ntiles;
     const int grid = std::min(jobs, res_grid());
-    launch_traced(leaf_res_kernel, dim3(grid), dim3(kResThreads), s, u, ntiles, jobs);
+    launch_traced(leaf_res_kernel, dim3(grid), dim3(kResThreads), s, leaf_last, u, ntiles, jobs);
   } else {
-    launch_traced((leaf_kernel<NQ, RT, true, F32>), dim3(u.L * u.tiles), dim3(kUThreads), s, u);
+    launch_traced((leaf_kernel<NQ, RT, true, F32>), dim3(u.L * u.tiles), dim3(kUThreads), s, leaf_last, u);
   }
-  const bool res_levels = K == 4 && NQ == 4 && node_res_ok(u);  // the top one also applies D
   for (int st = st0; st < u.L; st *= K) {
     UpdateParams v = u;
     v.stride = st;
     const int per = (u.L - st + K * st - 1) / (K * st);
+    const bool last = st * K >= u.L && !scale;
     if (res_levels) {
       const int ntiles = (int)((u.k + kResCols - 1) / kResCols);
       const int jobs = per * ntiles;
-      launch_traced(node_res_kernel, dim3(std::min(jobs, res_grid())), dim3(kResThreads), s, v, ntiles, jobs);
+      launch_traced(node_res_kernel, dim3(std::min(jobs, res_grid())), dim3(kResThreads), s, last, v, ntiles, jobs);
     } else {
-      launch_traced((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), s, v);
+      launch_traced((node_level_kernel<NQ, true, K>), dim3(per * u.tiles), dim3(kUThreads), s, last, v);
     }
   }
-  if (!(res_levels && u.L > 1)) launch_traced(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), s, u);
+  if (scale) launch_traced(scale_rows_kernel, dim3(u.tiles), dim3(kUThreads), s, true, u);
   return hipGetLastError();
 }
 
